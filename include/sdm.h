@@ -1,0 +1,281 @@
+/*
+ * sdm.h -- C ABI of the MI355X (gfx950) Super-Droplet Method coagulation
+ * library.  The routine set follows the backend API of Bartman & Arabas,
+ * "On the design of Monte-Carlo particle coagulation solver interface: a
+ * CPU/GPU Super-Droplet Method case study with PySDM" (arXiv:2101.06318),
+ * Sec. 3: four data structures (Storage, IndexedStorage, Index,
+ * PairIndicator) and the routines of the timestep workflow figure.
+ *
+ * Conventions (every entry point):
+ *  - Return value: SDM_OK (0) or a negative sdm_status.  On an error nothing
+ *    has been enqueued on the stream and sdm_last_error() (thread-local)
+ *    describes it.
+ *  - Pointers named *_dev or documented as "device" are device pointers into
+ *    memory the caller owns (e.g. torch tensors' data_ptr()).  The library
+ *    never frees or retains them after the call returns.  All device work is
+ *    enqueued asynchronously on the caller's hipStream_t; no call blocks the
+ *    host except sdm_create, sdm_destroy, sdm_prepare_step, sdm_batch_create,
+ *    sdm_batch_destroy, sdm_autotune and sdm_read_errors.
+ *  - Counts that change on the device (the live count n_live) stay on the
+ *    device as int64_t*, so sequences of calls can be captured in a HIP graph
+ *    (after a first eager call with the same shapes; see sdm_prepare_step).
+ *  - Argument order: outputs, then in/out, then inputs, as the paper's
+ *    intent comments in the workflow figure.
+ *  - Types: sizes int64_t; SD ids uint32_t; cell ids int32_t;
+ *    multiplicities xi uint64_t; attributes double, laid out row-major as
+ *    attr[n_attr][attr_stride] (structure of arrays, Sec. 3.1); row 0 is the
+ *    particle volume [m^3] the coalescence kernel reads.
+ *  - Device-side anomalies are not call errors.  Collision statistics go
+ *    into an optional caller-provided uint64_t counters_dev[8] (indices
+ *    SDM_CNT_*, added to, never reset); malformed device data (a cell id out
+ *    of range) is recorded in the context and reported by sdm_read_errors().
+ *
+ * Uniform random numbers (the paper names only its CURandRTC source): U =
+ * (w >> 11) * 2^-53, w the 64-bit word of element e of Philox4x32-10 with
+ * counter (e >> 1, step, stream, run) and key (lo32(seed), hi32(seed));
+ * even e takes output words 0-1, odd e words 2-3 (high word first).
+ */
+#ifndef SDM_H
+#define SDM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDM_ABI_VERSION 1
+
+typedef enum {
+    SDM_OK = 0,
+    SDM_E_INVALID = -1,      /* null pointer, size or enum out of range      */
+    SDM_E_HIP = -2,          /* HIP runtime or launch error                  */
+    SDM_E_NOMEM = -3,        /* device allocation failed                     */
+    SDM_E_UNSUPPORTED = -4,  /* size beyond what the context was created for */
+    SDM_E_STATE = -5         /* context misuse                               */
+} sdm_status;
+
+/* Random streams: Philox counter word 2. */
+enum { SDM_STREAM_SHUFFLE = 0, SDM_STREAM_GAMMA = 1, SDM_STREAM_INIT = 2,
+       SDM_STREAM_REASSIGN = 3, SDM_STREAM_MLP = 4 };
+
+/* Coalescence kernels a(v1, v2); p[] are the kernel parameters.
+ *  GOLOVIN        b (v1 + v2)                      p[0] = b [1/s]
+ *  GEOMETRIC      E pi (r1 + r2)^2 |w(r1) - w(r2)| p[0] = E (efficiency)
+ *                 r = cbrt(0.75 v / pi) (Newton cube root, 8 IEEE steps),
+ *                 w(r) = 1.19e8 r^2 (r < 40 um), 8e3 r (r < 600 um),
+ *                 201 sqrt(r) otherwise [m/s]
+ *  CONSTANT       p[0]
+ *  MULTIPLICATIVE p[0] v1 v2
+ * (Golovin, constant and multiplicative: Sec. 2.1; gravitational: Sec. 4.) */
+enum { SDM_KERNEL_GOLOVIN = 0, SDM_KERNEL_GEOMETRIC = 1,
+       SDM_KERNEL_CONSTANT = 2, SDM_KERNEL_MULTIPLICATIVE = 3 };
+
+/* Counter slots (uint64_t counters_dev[8]). */
+enum { SDM_CNT_PAIRS = 0,      /* flagged pairs visited                      */
+       SDM_CNT_COLLISIONS = 1, /* pairs with gamma-tilde > 0                 */
+       SDM_CNT_CAPPED = 2,     /* gamma-tilde < gamma (eq. 4 cap active)     */
+       SDM_CNT_ZEROED = 3,     /* eq. (6) split with xi_k = 1: xi_j -> 0     */
+       SDM_CNT_GAMMA_GE2 = 4,  /* pairs with gamma >= 2                      */
+       SDM_CNT_N = 8 };
+
+typedef struct sdm_ctx sdm_ctx;
+typedef struct sdm_batch sdm_batch;
+
+typedef struct {
+    int32_t id;              /* SDM_KERNEL_*                                 */
+    int32_t reserved;
+    double  p[4];            /* kernel parameters (see above)                */
+} sdm_kernel;
+
+typedef struct {
+    uint64_t        seed;
+    uint32_t        run;
+    uint32_t        step;    /* timestep index; ignored if step_dev != NULL  */
+    const uint32_t *step_dev;/* optional device pointer to the step index,   */
+                             /* so a captured graph can advance it           */
+} sdm_rng;
+
+/* ---------------------------------------------------------------- setup */
+int         sdm_abi_version(void);
+const char *sdm_last_error(void);
+
+/* Creates a context on the current HIP device for up to n_sd_max SD slots,
+ * n_cell_max cells and n_attr_max attribute rows.  The context owns its
+ * device workspace (sort buckets, scan buffers, counters).  Blocking. */
+int sdm_create(sdm_ctx **ctx, int64_t n_sd_max, int32_t n_cell_max,
+               int32_t n_attr_max);
+int sdm_destroy(sdm_ctx *ctx);
+
+/* Reads and clears the context's device error flags (blocking).
+ * *flags bit 0: a cell id outside [0, n_cell) was seen (that SD was left out
+ * of the sort). */
+int sdm_read_errors(sdm_ctx *ctx, uint32_t *flags);
+
+/* Testing hook: rebuilds the sort plans with bucket regions of bucket_cap
+ * slots (0 = automatic) and a group capacity of group_cap records (< 0 =
+ * automatic), so that the overflow list and the global-memory sort path
+ * run on ordinary inputs.  Results are identical; only speed changes.
+ * Blocking. */
+int sdm_set_plan_limits(sdm_ctx *ctx, int32_t bucket_cap, int32_t group_cap);
+
+/* ------------------------------------------------------------ R2 urand */
+/* u01[e] = U(seed, run, step, stream_id, e) for e in [0, n).
+ * u01: device, n doubles, written. */
+int sdm_urand(sdm_ctx *ctx, double *u01, int64_t n, const sdm_rng *rng,
+              uint32_t stream_id, hipStream_t stream);
+
+/* --------------------------------------------------- Step 0 (R1) */
+/* Stable removal of zero-multiplicity SDs from the Index (Sec. 3.2, Step 0).
+ * idx: device uint32[n_sd_max], in/out (entries [0, *n_live_dev) used);
+ * n_live_dev: device int64, in/out; xi: device uint64 indexed by SD id. */
+int sdm_remove_if_equal_0(sdm_ctx *ctx, uint32_t *idx, int64_t *n_live_dev,
+                          const uint64_t *xi, hipStream_t stream);
+
+/* --------------------------------------------------- Step 1 (R3, R4) */
+/* Stable counting sort of idx[0:n_live] by cell_id[idx[i]] (the Index's
+ * sort-by-key on the cell id, Sec. 3.1).
+ * cell_start: device uint32[n_cell+1], out: cell_start[c] = number of live
+ * SDs in cells < c.  idx: in/out.  cell_id: device int32 by SD id. */
+int sdm_cell_sort(sdm_ctx *ctx, uint32_t *cell_start, uint32_t *idx,
+                  const int64_t *n_live_dev, const int32_t *cell_id,
+                  int32_t n_cell, hipStream_t stream);
+
+/* shuffle_per_cell (Sec. 3.2, Step 1): sorts idx[0:n_live] by
+ * (cell_id[s], floor(u_s * 2^53), s) ascending, the random-key sort the
+ * paper uses on the GPU.  u_s = u01_by_sd[s] (device double by SD id) or,
+ * if u01_by_sd is NULL, U(rng, SDM_STREAM_SHUFFLE, s) generated inline
+ * (values outside [0, 1) are clamped to that range).  idx entries must be
+ * valid SD ids (< n_sd_max).
+ * cell_start: out as above.  cell_idx: optional device int32[n_cell] cell
+ * traversal order (scheduling hint only; results do not depend on it). */
+int sdm_shuffle_per_cell(sdm_ctx *ctx, uint32_t *cell_start, uint32_t *idx,
+                         const int64_t *n_live_dev, const int32_t *cell_idx,
+                         const int32_t *cell_id, int32_t n_cell,
+                         const double *u01_by_sd, const sdm_rng *rng,
+                         hipStream_t stream);
+
+/* flag_pairs (PairIndicator, Sec. 3.1; GPU listing Fig. 3):
+ * pair_flag[i] = i+1 < n_live && cell(idx[i+1]) == cell(idx[i]) &&
+ *                (i - cell_start[cell(idx[i])]) even.
+ * pair_flag: device uint8[n_sd_max], out (entries [0, n_live)). */
+int sdm_flag_pairs(sdm_ctx *ctx, uint8_t *pair_flag, const int32_t *cell_id,
+                   const int32_t *cell_idx, const uint32_t *cell_start,
+                   const uint32_t *idx, const int64_t *n_live_dev,
+                   hipStream_t stream);
+
+/* --------------------------------------------------- Step 2 (R5-R7), eq. 3 */
+/* The pair opened at flagged position i owns slot floor(i/2) of pair_prob
+ * (device double[n_sd_max/2]); slots [0, floor(n_live/2)) with no flagged
+ * position are set to 0 by coalescence_kernel and left alone by the rest.
+ * coalescence_kernel: p = a(v_j, v_k).
+ * times_max:          p = p * max(xi_j, xi_k).
+ * normalize:          p = p * ((dt / dv_per_cell[c]) * F(n_c)),
+ *                     F(n) = ((n^2 - n)/2) / floor(n/2) in integers.
+ * pair_rate:          the three in one pass, same result bit for bit.      */
+int sdm_coalescence_kernel(sdm_ctx *ctx, double *pair_prob,
+                           const uint8_t *pair_flag, const double *volume,
+                           const uint32_t *idx, const int64_t *n_live_dev,
+                           const sdm_kernel *kernel, hipStream_t stream);
+int sdm_times_max(sdm_ctx *ctx, double *pair_prob, const uint64_t *xi,
+                  const uint8_t *pair_flag, const uint32_t *idx,
+                  const int64_t *n_live_dev, hipStream_t stream);
+int sdm_normalize(sdm_ctx *ctx, double *pair_prob, double dt,
+                  const double *dv_per_cell, const int32_t *cell_id,
+                  const int32_t *cell_idx, const uint32_t *cell_start,
+                  const uint8_t *pair_flag, const uint32_t *idx,
+                  const int64_t *n_live_dev, hipStream_t stream);
+int sdm_pair_rate(sdm_ctx *ctx, double *pair_prob, double dt,
+                  const double *dv_per_cell, const uint8_t *pair_flag,
+                  const double *volume, const uint64_t *xi,
+                  const int32_t *cell_id, const uint32_t *cell_start,
+                  const uint32_t *idx, const int64_t *n_live_dev,
+                  const sdm_kernel *kernel, hipStream_t stream);
+
+/* --------------------------------------------------- Step 3 (R8, R9) */
+/* compute_gamma: pair_prob[q] = ceil(pair_prob[q] - phi_q) in place for
+ * q in [0, floor(n_live/2)); phi_q = u01_by_slot[q] or, if NULL,
+ * U(rng, SDM_STREAM_GAMMA, q). */
+int sdm_compute_gamma(sdm_ctx *ctx, double *pair_prob,
+                      const double *u01_by_slot, const sdm_rng *rng,
+                      const int64_t *n_live_dev, hipStream_t stream);
+
+/* update_attributes, eqs. (4)-(6): for every flagged i, j and k are the SDs
+ * at i and i+1, swapped so that xi_j >= xi_k (a tie keeps j at i);
+ * g = min(gamma, floor(xi_j/xi_k)) with gamma read from slot floor(i/2)
+ * (NaN and values < 1 read as 0, >= 2^64 saturate); case 1 (xi_j - g xi_k >
+ * 0): xi_j -= g xi_k, A_k += g A_j; case 2: xi_j = floor(xi_k/2),
+ * xi_k -= xi_j, A_j = A_j g + A_k, A_k = A_j.  xi, attr: in/out, by SD id.
+ * counters_dev: optional uint64[8]. */
+int sdm_update_attributes(sdm_ctx *ctx, uint64_t *xi, double *attr,
+                          int32_t n_attr, int64_t attr_stride,
+                          const double *gamma, const uint8_t *pair_flag,
+                          const uint32_t *idx, const int64_t *n_live_dev,
+                          uint64_t *counters_dev, hipStream_t stream);
+
+/* --------------------------------------------------- fused timestep */
+/* State of one run (Sec. 3.1 state listing).  All pointers are device
+ * pointers owned by the caller. */
+typedef struct {
+    int64_t   n_sd;          /* SD slots                                    */
+    int32_t   n_cell;
+    int32_t   n_attr;
+    int64_t   attr_stride;   /* >= n_sd                                     */
+    uint64_t *xi;            /* [n_sd]            in/out                    */
+    double   *attr;          /* [n_attr][stride]  in/out                    */
+    const int32_t *cell_id;  /* [n_sd] or NULL (every SD in cell 0)         */
+    uint32_t *idx;           /* [n_sd]            out: sorted live SDs      */
+    int64_t  *n_live_dev;    /* [1]               out                       */
+    uint32_t *cell_start;    /* [n_cell+1]        out                       */
+    uint64_t *counters_dev;  /* [8] or NULL       added to                  */
+    double   *gamma_out;     /* [n_sd/2] or NULL: slot gammas (diagnostic)  */
+} sdm_state;
+
+typedef struct {
+    double            dt;            /* [s]                                 */
+    const double     *dv_per_cell;   /* device [n_cell], or NULL => dv      */
+    double            dv;            /* [m^3] used when dv_per_cell is NULL */
+    sdm_kernel        kernel;
+    sdm_rng           rng;
+    uint32_t         *step_advance;  /* optional device counter incremented */
+                                     /* by one at the end of the step       */
+    double            expected_per_cell; /* planning hint (0 => n_sd/n_cell)*/
+    hipEvent_t        events[4];     /* optional (NULL entries skipped):    */
+                                     /* recorded on the stream before the   */
+                                     /* scatter, group and seam kernels and */
+                                     /* after the seam kernel, for timing   */
+} sdm_step_params;
+
+/* One whole timestep (workflow figure, Steps 0-3) in three kernels, with the
+ * result of running the routines above in the paper's order with inline
+ * random numbers: the live set is {s : xi[s] > 0} (Step 0), idx receives
+ * the live SDs sorted by (cell, shuffle key, s), the pairs and slots are
+ * those of flag_pairs, gamma draws U(rng, SDM_STREAM_GAMMA, slot).  The
+ * incoming idx order is not read.  The first call for a given shape builds
+ * the plan (allocating, not capturable); sdm_prepare_step does that
+ * explicitly so the step can then be captured. */
+int sdm_prepare_step(sdm_ctx *ctx, const sdm_state *st,
+                     const sdm_step_params *p);
+int sdm_step(sdm_ctx *ctx, const sdm_state *st, const sdm_step_params *p,
+             hipStream_t stream);
+
+/* --------------------------------------------------- moments */
+/* M[c][k] = sum over live s in cell c of xi_s v_s^k / dV_c, k = 0, 1, 2.
+ * Needs idx sorted by cell with cell_start (as after a step).  M: device
+ * double[n_cell][3], out.  Sum order is fixed (deterministic). */
+int sdm_moments(sdm_ctx *ctx, double *M, const uint64_t *xi,
+                const double *volume, const uint32_t *idx,
+                const uint32_t *cell_start, int32_t n_cell,
+                const double *dv_per_cell, double dv, hipStream_t stream);
+
+/* Grid workload driver (advection stand-in): cell_id[s] =
+ * floor(U(seed, 0, step, SDM_STREAM_REASSIGN, s) * n_cell), n_cell a power
+ * of two.  cell_id: device int32[n_sd], out. */
+int sdm_reassign(sdm_ctx *ctx, int32_t *cell_id, int64_t n_sd, int32_t n_cell,
+                 const sdm_rng *rng, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDM_H */

@@ -1,0 +1,287 @@
+// Device-side building blocks of the SDM coagulation step on gfx950:
+// counter-based uniforms, coalescence kernels and the pairwise collision
+// update.  Definitions follow arXiv:2101.06318 (eqs. 3-6) and the uniform
+// stream described in include/sdm.h.  Compiled with -ffp-contract=off so
+// every floating-point operation below is one IEEE binary64 operation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdm {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11).  With a wave-uniform key the round
+// keys live in scalar registers; each round is two 32x32->64 multiplies.
+struct Block4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                         uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// 64-bit words of elements 2m (lo) and 2m+1 (hi) of a stream.
+struct WordPair {
+    uint64_t even, odd;
+};
+
+__device__ __forceinline__ WordPair philox_words(uint64_t seed, uint32_t run,
+                                                 uint32_t step, uint32_t stream,
+                                                 uint64_t pair_index)
+{
+    const Block4 b = philox((uint32_t)pair_index, step, stream, run,
+                            (uint32_t)seed, (uint32_t)(seed >> 32));
+    return WordPair{((uint64_t)b.w0 << 32) | b.w1, ((uint64_t)b.w2 << 32) | b.w3};
+}
+
+__device__ __forceinline__ uint64_t philox_word(uint64_t seed, uint32_t run,
+                                                uint32_t step, uint32_t stream,
+                                                uint64_t e)
+{
+    const WordPair w = philox_words(seed, run, step, stream, e >> 1);
+    return (e & 1) ? w.odd : w.even;
+}
+
+// 53-bit uniform in [0, 1) from a Philox word.
+__device__ __forceinline__ double word_to_uniform(uint64_t w)
+{
+    return (double)(w >> 11) * 0x1p-53;
+}
+
+// Sort key of a given uniform: floor(u * 2^53); values outside [0, 1)
+// (and NaN) are clamped into the key range.
+__device__ __forceinline__ uint64_t uniform_to_key(double u)
+{
+    if (!(u > 0.0))
+        return 0;
+    if (u >= 1.0)
+        return (1ull << 53) - 1;
+    return (uint64_t)(u * 9007199254740992.0);
+}
+
+// ------------------------------------------------------------- kernels
+enum { KERNEL_GOLOVIN = 0, KERNEL_GEOMETRIC = 1, KERNEL_CONSTANT = 2,
+       KERNEL_MULTIPLICATIVE = 3 };
+
+struct KernelDesc {
+    int32_t id;
+    int32_t reserved;
+    double p[4];
+};
+
+#define SDM_PI_D 3.141592653589793
+
+// Cube root by Newton's iteration y <- (2y + x/y^2)/3 from the power of two
+// nearest below x^(1/3); 8 steps reach full binary64 precision over the
+// normal range.  Only +, *, / and exact scalings, so host and device agree
+// bit for bit.
+__device__ __forceinline__ double cbrt_newton(double x)
+{
+    if (x == 0.0)
+        return 0.0;
+    int e;
+    (void)frexp(x, &e);
+    int q = e / 3;
+    if (e % 3 < 0)
+        q -= 1;
+    double y = ldexp(1.0, q);
+#pragma unroll
+    for (int it = 0; it < 8; ++it)
+        y = (2.0 * y + x / (y * y)) / 3.0;
+    return y;
+}
+
+// Three-regime power-law terminal velocity [m/s] of a drop of radius r [m].
+__device__ __forceinline__ double terminal_velocity(double r)
+{
+    if (r < 40.0e-6)
+        return 1.19e8 * (r * r);
+    if (r < 600.0e-6)
+        return 8.0e3 * r;
+    return 201.0 * sqrt(r);
+}
+
+__device__ __forceinline__ double kernel_value(const KernelDesc &k, double v1,
+                                               double v2)
+{
+    switch (k.id) {
+    case KERNEL_GOLOVIN:
+        return k.p[0] * (v1 + v2);
+    case KERNEL_GEOMETRIC: {
+        const double r1 = cbrt_newton((0.75 * v1) / SDM_PI_D);
+        const double r2 = cbrt_newton((0.75 * v2) / SDM_PI_D);
+        const double w1 = terminal_velocity(r1);
+        const double w2 = terminal_velocity(r2);
+        const double rs = r1 + r2;
+        return ((SDM_PI_D * (rs * rs)) * fabs(w1 - w2)) * k.p[0];
+    }
+    case KERNEL_CONSTANT:
+        return k.p[0];
+    case KERNEL_MULTIPLICATIVE:
+        return k.p[0] * (v1 * v2);
+    default:
+        return 0.0;
+    }
+}
+
+// F(n) = ((n^2 - n)/2) / floor(n/2): n - 1 for even n, n for odd n.
+__device__ __forceinline__ uint64_t pair_scale(uint64_t n)
+{
+    if (n < 2)
+        return 0;
+    return (n & 1) ? n : n - 1;
+}
+
+// Rate gamma as a count: NaN, negatives and -0.0 read as 0; >= 2^64 saturates.
+__device__ __forceinline__ uint64_t gamma_count(double g)
+{
+    if (!(g >= 1.0))
+        return 0;
+    if (g >= 18446744073709551616.0)
+        return ~0ull;
+    return (uint64_t)g;
+}
+
+// Collision statistics gathered per thread, reduced per workgroup.
+struct Stats {
+    uint32_t pairs, coll, capped, zeroed, ge2;
+};
+
+// Outcome of eqs. (4)-(6) for one pair.  (a, b) are the SDs at the opening
+// and the following sorted positions.  Returns g (gamma-tilde); on g > 0 it
+// fills the new multiplicities and tells which SD is j (the larger).
+struct Collision {
+    uint64_t g;
+    uint64_t xj_new, xk_new;
+    bool a_is_j;
+    bool split;  // case 2 (equal-multiplicity split)
+};
+
+__device__ __forceinline__ Collision collide(uint64_t xa, uint64_t xb, double gamma,
+                                             Stats &st)
+{
+    Collision c;
+    c.a_is_j = !(xa < xb);
+    const uint64_t xj = c.a_is_j ? xa : xb;
+    const uint64_t xk = c.a_is_j ? xb : xa;
+    st.pairs += 1;
+    c.g = 0;
+    c.split = false;
+    c.xj_new = xj;
+    c.xk_new = xk;
+    if (xk == 0)
+        return c;
+    const uint64_t G = gamma_count(gamma);
+    if (G == 0)
+        return c;
+    // g = min(G, floor(xj/xk)); the 64-bit division is only needed when
+    // G >= 2, since xj >= xk makes floor(xj/xk) >= 1.
+    uint64_t g = 1;
+    if (G >= 2) {
+        st.ge2 += 1;
+        const uint64_t ratio = xj / xk;
+        g = G < ratio ? G : ratio;
+        if (g < G)
+            st.capped += 1;
+    }
+    st.coll += 1;
+    c.g = g;
+    const uint64_t d = xj - g * xk;
+    if (d > 0) {
+        c.xj_new = d;
+    } else {
+        const uint64_t h = xk / 2;
+        c.xj_new = h;
+        c.xk_new = xk - h;
+        c.split = true;
+        if (h == 0)
+            st.zeroed += 1;
+    }
+    return c;
+}
+
+// Attribute update of eqs. (5)/(6) for one attribute row.
+__device__ __forceinline__ void collide_attr(double &Aj, double &Ak, uint64_t g,
+                                             bool split)
+{
+    const double gd = (double)g;
+    if (!split) {
+        Ak = Ak + gd * Aj;
+    } else {
+        Aj = Aj * gd + Ak;
+        Ak = Aj;
+    }
+}
+
+// Writes the outcome of a pair with g > 0 to the global state.
+__device__ __forceinline__ void apply_collision(const Collision &c, uint32_t sa,
+                                                uint32_t sb, uint64_t *xi,
+                                                double *attr, int n_attr,
+                                                int64_t stride)
+{
+    const uint32_t sj = c.a_is_j ? sa : sb;
+    const uint32_t sk = c.a_is_j ? sb : sa;
+    xi[sj] = c.xj_new;
+    xi[sk] = c.xk_new;
+    for (int r = 0; r < n_attr; ++r) {
+        double *A = attr + (int64_t)r * stride;
+        double Aj = A[sj], Ak = A[sk];
+        collide_attr(Aj, Ak, c.g, c.split);
+        A[sj] = Aj;
+        A[sk] = Ak;
+    }
+}
+
+// Workgroup reduction of the statistics into counters[8] (one atomic per
+// nonzero slot per workgroup).  `red` is LDS scratch of 5*(threads/64) words.
+template <int THREADS>
+__device__ __forceinline__ void flush_stats(const Stats &st, uint64_t *counters,
+                                            uint32_t *red)
+{
+    constexpr int W = THREADS / 64;
+    uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            v[i] += __shfl_xor(v[i], o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            red[i * W + wid] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5 && counters) {
+        uint64_t s = 0;
+        for (int w = 0; w < W; ++w)
+            s += red[threadIdx.x * W + w];
+        if (s)
+            atomicAdd((unsigned long long *)&counters[threadIdx.x],
+                      (unsigned long long)s);
+    }
+}
+
+__device__ __forceinline__ uint32_t step_of(uint32_t step, const uint32_t *step_dev)
+{
+    return step_dev ? *step_dev : step;
+}
+
+}  // namespace sdm

@@ -1,0 +1,214 @@
+"""GPU parity of the fused timestep (sdm_step) against the oracle's
+routine-by-routine timestep (workflow figure of arXiv:2101.06318): bit-exact
+multiplicities, attributes, permutation, live count, cell starts, slot
+gammas and counters."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_06318_amd import workloads
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sdm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2101_06318_amd as m
+    m.lib()
+    return m
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _check(st, ref, n_sd, what=""):
+    n = int(host(st.n_live)[0])
+    assert n == ref["n_live"], what
+    assert np.array_equal(host(st.xi), ref["xi"]), what
+    got_attr = host(st.attr)
+    if not np.array_equal(got_attr, ref["attr"]):
+        rel = np.abs(got_attr - ref["attr"]) / np.maximum(np.abs(ref["attr"]), 1e-300)
+        assert rel.max() <= 1e-12, (what, rel.max())
+        raise AssertionError("attributes differ (within 1e-12) but bits differ: %s" % what)
+    assert np.array_equal(host(st.idx, np.uint32)[:n], ref["idx"][:n]), what
+    assert np.array_equal(host(st.cell_start, np.uint32), ref["cell_start"]), what
+    if st.gamma_out is not None:
+        g, rg = host(st.gamma_out), ref["gamma"]
+        bad = np.nonzero(g != rg)[0]
+        assert bad.size == 0, (what, bad[:5], g[bad[:5]], rg[bad[:5]])
+
+
+def _run_pair(sdm, ctx, w, steps, seed, kparams=None, gamma=True, reassign=False, cell_id=None,
+              dead=None, run=0):
+    n_sd = w["n_sd"]
+    kp = kparams if kparams is not None else w["kparams"]
+    xi = w["xi"].copy()
+    if dead is not None:
+        xi[dead] = 0
+    cid = w["cell_id"] if cell_id is None else cell_id
+    n_cell = w["n_cell"]
+    st = sdm.State(xi, w["attr"], cid if n_cell > 1 else None, n_cell, want_gamma=gamma)
+    dv = dev(np.asarray(w["dv"], np.float64))
+    k = sdm.kernel(w["kernel_id"], kp)
+    ref = dict(xi=xi, attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
+    ref["n_live"] = n_sd
+    cnt = np.zeros(8, np.uint64)
+    cur_cid = cid
+    for t in range(steps):
+        if reassign:
+            cur_cid = oracle.reassign(n_sd, n_cell, seed, t)
+            ctx.reassign(st.cell_id, n_sd, n_cell, sdm.rng(seed, 0, t))
+        ctx.step(st, w["dt"], k, sdm.rng(seed, run, t), dv_per_cell=dv)
+        ref = oracle.step(ref["xi"], ref["attr"], cur_cid if n_cell > 1 else None, n_cell, w["dv"],
+                          ref["idx"], ref["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
+                          kparams=kp, seed=seed, run=run, step=t, counters=cnt,
+                          want_gamma=gamma)
+        cnt = ref["counters"]
+        _sync()
+        _check(st, ref, n_sd, "step %d" % t)
+    assert np.array_equal(host(st.counters), cnt)
+    return st, ref
+
+
+@pytest.mark.parametrize("n_sd", [1, 2, 3, 64, 4095, 8192, 8192 + 131, 40000])
+def test_step_single_cell(sdm, n_sd):
+    w = workloads.box(n_sd, seed=n_sd)
+    ctx = sdm.Context(n_sd, 1, 1)
+    # kernel scaled up so collisions, gamma >= 2 and caps occur within a few steps
+    _run_pair(sdm, ctx, w, 4, seed=3, kparams=[1500.0 * 300])
+    ctx.close()
+
+
+def test_step_with_dead_sds_and_removals(sdm):
+    n_sd = 6000
+    w = workloads.box(n_sd, seed=1)
+    w["xi"] = np.random.default_rng(0).integers(1, 4, n_sd).astype(np.uint64)  # xi_k = 1 splits
+    ctx = sdm.Context(n_sd, 1, 1)
+    dead = np.random.default_rng(1).random(n_sd) < 0.2
+    st, ref = _run_pair(sdm, ctx, w, 6, seed=9, kparams=[5.0e14], dead=dead)
+    assert ref["counters"][oracle.CNT_ZEROED] > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx", [4, 32])
+def test_step_grid_geometric_with_reassignment(sdm, nx):
+    w = workloads.grid(seed=3, nx=nx, ny=nx)
+    ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    _run_pair(sdm, ctx, w, 3, seed=3, kparams=[50.0], reassign=True)
+    ctx.close()
+
+
+def test_step_grid_static_cells(sdm):
+    w = workloads.grid(seed=5, nx=64, ny=64, mean_per_cell=20)
+    ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    _run_pair(sdm, ctx, w, 3, seed=5, kparams=[100.0])
+    ctx.close()
+
+
+@pytest.mark.parametrize("caps", [(32, -1), (0, 64), (16, 40)])
+def test_step_overflow_and_global_sort_paths(sdm, caps):
+    """Tiny bucket regions / group capacities force the overflow list and the
+    global-memory bitonic sort; the result must not change."""
+    w = workloads.box(20000, seed=2)
+    ctx = sdm.Context(20000, 1, 1)
+    ctx.set_plan_limits(*caps)
+    _run_pair(sdm, ctx, w, 3, seed=4, kparams=[1500.0 * 300])
+    g = workloads.grid(seed=7, nx=8, ny=8)
+    ctx2 = sdm.Context(g["n_sd"], g["n_cell"], 2)
+    ctx2.set_plan_limits(*caps)
+    _run_pair(sdm, ctx2, g, 2, seed=7, kparams=[50.0], reassign=True)
+    ctx.close()
+    ctx2.close()
+
+
+def test_golovin_box_trajectory_bit_exact(sdm):
+    """The paper's validation box at 2^13 SDs for 3600 steps (dt = 1 s)."""
+    n_sd = 8192
+    w = workloads.box(n_sd, seed=1)
+    ctx = sdm.Context(n_sd, 1, 1)
+    st = sdm.State(w["xi"], w["attr"], None, 1)
+    k = sdm.kernel(0, w["kparams"])
+    for t in range(3600):
+        ctx.step(st, 1.0, k, sdm.rng(1, 0, t), dv=w["dv"][0])
+    _sync()
+    ref = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
+    for t in range(3600):
+        ref = oracle.step(ref["xi"], ref["attr"], None, 1, w["dv"], ref["idx"], ref["n_live"],
+                          dt=1.0, kernel_id=0, kparams=w["kparams"], seed=1, run=0, step=t)
+    _check(st, ref, n_sd, "t=3600")
+    ctx.close()
+
+
+def test_full_size_box_2_22(sdm):
+    """The throughput configuration (2^22 SDs) in the launch configuration
+    the benchmark times: two whole steps against the oracle."""
+    n_sd = 1 << 22
+    w = workloads.box(n_sd, seed=2)
+    ctx = sdm.Context(n_sd, 1, 1)
+    t0 = time.time()
+    _run_pair(sdm, ctx, w, 2, seed=2, gamma=True)
+    print("2^22 parity: %.1f s" % (time.time() - t0))
+    ctx.close()
+
+
+def test_graph_replay_matches_eager(sdm):
+    import torch
+    n_sd = 30000
+    w = workloads.box(n_sd, seed=4)
+    k = sdm.kernel(0, [1500.0 * 100])
+    ctx = sdm.Context(n_sd, 1, 1)
+    a = sdm.State(w["xi"], w["attr"], None, 1)
+    b = sdm.State(w["xi"], w["attr"], None, 1)
+    step_dev = dev(np.array([0], np.uint32))
+    s = torch.cuda.Stream()
+    ctx.prepare_step(b, 1.0, k, sdm.rng(4, 0, 0, step_dev=step_dev), dv=w["dv"][0])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ctx.step(b, 1.0, k, sdm.rng(4, 0, 0, step_dev=step_dev), dv=w["dv"][0],
+                     step_advance=step_dev, stream=s)
+    _sync()
+    for t in range(5):
+        ctx.step(a, 1.0, k, sdm.rng(4, 0, t), dv=w["dv"][0])
+        _sync()
+        g.replay()
+        _sync()
+        for name in ("xi", "attr", "idx", "n_live", "cell_start"):
+            assert np.array_equal(host(getattr(a, name)), host(getattr(b, name))), (t, name)
+        assert int(host(step_dev)[0]) == t + 1
+    ctx.close()
+
+
+def test_run_twice_deterministic(sdm):
+    import torch
+    w = workloads.grid(seed=11, nx=16, ny=16)
+    outs = []
+    for _ in range(2):
+        ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+        st = sdm.State(w["xi"], w["attr"], w["cell_id"], w["n_cell"])
+        for t in range(5):
+            ctx.step(st, 1.0, sdm.kernel(1, [50.0]), sdm.rng(11, 0, t), dv_per_cell=dev(w["dv"]))
+        _sync()
+        outs.append((host(st.xi).copy(), host(st.attr).copy(), host(st.idx).copy()))
+        ctx.close()
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
+
+
+def test_bad_cell_id_is_reported(sdm):
+    w = workloads.grid(seed=1, nx=4, ny=4)
+    cid = w["cell_id"].copy()
+    cid[5] = w["n_cell"] + 3
+    ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    st = sdm.State(w["xi"], w["attr"], cid, w["n_cell"])
+    ctx.step(st, 1.0, sdm.kernel(1, [1.0]), sdm.rng(1, 0, 0), dv_per_cell=dev(w["dv"]))
+    assert ctx.read_errors() & 1
+    assert int(host(st.n_live)[0]) == w["n_sd"] - 1
+    ctx.close()
