@@ -5,9 +5,11 @@ N0 = 2^23 m^-3, exponential volumes with mean (4 pi/3)(30.531 um)^3,
 b = 1500 1/s, dt = 1 s), scaled to 2^22 super-droplets, synthetic, seed 2.
 A step is one whole timestep (Steps 0-3: removal, shuffle, pairing, pair
 probability, gamma, collision update) through the C ABI (sdm_step, three
-kernels).  W warm-up steps run first; then exactly K steps run as one
-replay of a captured HIP graph, bracketed by synchronisation, with HIP
-events recorded between the kernels of every step on the launch stream.
+kernels).  W warm-up steps run first; then exactly K steps are timed on
+one stream, bracketed by synchronisation, with HIP events recorded by the
+library before and after each of its kernels on that stream (per-kernel
+durations for the roofline).  The same K steps are then also captured in a
+HIP graph and replayed once; that time is reported as graph_ms_per_step.
 
 Prints one JSON line (metric, value, ..., roofline, cpu_baseline).
 """
@@ -64,6 +66,40 @@ def traffic_record(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+class HipEvent:
+    """A HIP event created through the runtime the library uses; the
+    library records it on the launch stream between its kernels."""
+
+    def __init__(self, lib):
+        import ctypes
+        self._lib = lib
+        h = ctypes.c_void_p()
+        fn = lib.hipEventCreate
+        fn.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        fn.restype = ctypes.c_int
+        if fn(ctypes.byref(h)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        self.cuda_event = h.value
+
+    def elapsed_ms(self, other):
+        import ctypes
+        f = ctypes.c_float(0.0)
+        fn = self._lib.hipEventElapsedTime
+        fn.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        fn.restype = ctypes.c_int
+        rc = fn(ctypes.byref(f), ctypes.c_void_p(self.cuda_event),
+                ctypes.c_void_p(other.cuda_event))
+        if rc != 0:
+            raise RuntimeError("hipEventElapsedTime failed (%d)" % rc)
+        return float(f.value)
+
+    def destroy(self):
+        import ctypes
+        fn = self._lib.hipEventDestroy
+        fn.argtypes = [ctypes.c_void_p]
+        fn(ctypes.c_void_p(self.cuda_event))
+
+
 def cpu_baseline(w, n_steps):
     import numpy as np
 
@@ -91,7 +127,7 @@ def main():
     ap.add_argument("--log2-n-sd", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
+    ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the SDM step of one run on one "
@@ -126,46 +162,54 @@ def main():
     pairs0 = int(st.counters.cpu().numpy()[sdm.CNT_PAIRS])
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    L = sdm.lib()
+    ev = [[HipEvent(L) for _ in range(4)] for _ in range(K)]
     stream = torch.cuda.Stream()
-    graph = None
-    mode = "graph"
-    if not args.eager:
-        try:
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.stream(stream):
-                with torch.cuda.graph(graph, stream=stream):
-                    for t in range(K):
-                        ctx.step(st, w["dt"], k, r, stream=stream, events=ev[t], **kw)
-            torch.cuda.synchronize()
-        except Exception as e:  # capture unsupported: time eager launches
-            print("bench: graph capture failed (%s); timing eager launches" % e,
-                  file=sys.stderr, flush=True)
-            graph = None
-    if graph is None:
-        mode = "eager"
 
+    # Timed region: exactly K steps on one stream; the library records HIP
+    # events before/after each of its three kernels on that stream.
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         start.record(stream)
-        if graph is not None:
-            graph.replay()
-        else:
-            for t in range(K):
-                ctx.step(st, w["dt"], k, r, stream=stream, events=ev[t], **kw)
+        for t in range(K):
+            ctx.step(st, w["dt"], k, r, stream=stream, events=ev[t], **kw)
         end.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
     per = {"k_scatter": [], "k_group": [], "k_seams": []}
     for t in range(K):
-        per["k_scatter"].append(ev[t][0].elapsed_time(ev[t][1]))
-        per["k_group"].append(ev[t][1].elapsed_time(ev[t][2]))
-        per["k_seams"].append(ev[t][2].elapsed_time(ev[t][3]))
+        per["k_scatter"].append(ev[t][0].elapsed_ms(ev[t][1]))
+        per["k_group"].append(ev[t][1].elapsed_ms(ev[t][2]))
+        per["k_seams"].append(ev[t][2].elapsed_ms(ev[t][3]))
     avg_ms = {kname: float(np.mean(v)) for kname, v in per.items()}
 
     cnt = st.counters.cpu().numpy()
+    graph_ms = None
+    if not args.eager:
+        # Same K steps captured once in a HIP graph and replayed (reported
+        # beside the timed region; the step index advances on the device).
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(stream):
+                with torch.cuda.graph(g, stream=stream):
+                    for t in range(K):
+                        ctx.step(st, w["dt"], k, r, stream=stream, **kw)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            gs = torch.cuda.Event(enable_timing=True)
+            ge = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                gs.record(stream)
+                g.replay()
+                ge.record(stream)
+            torch.cuda.synchronize()
+            graph_ms = gs.elapsed_time(ge) / K
+            del g
+        except Exception as e:
+            print("bench: graph replay not measured (%s)" % e, file=sys.stderr, flush=True)
     pairs = int(cnt[sdm.CNT_PAIRS]) - pairs0
     f_coll = (int(cnt[sdm.CNT_COLLISIONS]) - coll0) / max(pairs, 1)
     n_live = int(st.n_live.item())
@@ -194,11 +238,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n_sd": n_sd, "cells": 1, "kernel": "golovin",
                    "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]),
-                   "seed": 2, "timing": mode, "n_live": n_live,
+                   "seed": 2, "timing": "eager, one stream, HIP events per kernel",
+                   "n_live": n_live,
                    "collision_fraction": f_coll},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_ms": avg_ms,
+        "graph_ms_per_step": graph_ms,
         "step_roofline": {"bound": "hbm", "bytes_per_step": ab["step"], "achieved": step_gbs,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": step_gbs / HBM_PEAK_GBS},
@@ -209,6 +255,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     else:
         out["cpu_baseline"] = None
+    for row in ev:
+        for e in row:
+            e.destroy()
     ctx.close()
     print(json.dumps(out), flush=True)
 

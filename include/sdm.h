@@ -113,12 +113,12 @@ int sdm_destroy(sdm_ctx *ctx);
  * of the sort). */
 int sdm_read_errors(sdm_ctx *ctx, uint32_t *flags);
 
-/* Testing hook: rebuilds the sort plans with bucket regions of bucket_cap
- * slots (0 = automatic) and a group capacity of group_cap records (< 0 =
- * automatic), so that the overflow list and the global-memory sort path
- * run on ordinary inputs.  Results are identical; only speed changes.
- * Blocking. */
-int sdm_set_plan_limits(sdm_ctx *ctx, int32_t bucket_cap, int32_t group_cap);
+/* Testing hook: rebuilds the sort plans with bucket_target expected SDs
+ * per key bucket (0 = automatic, 2048) and a group capacity of group_cap
+ * records (< 0 = automatic), so that cells spanning many groups, seams and
+ * the global-memory sort path run on ordinary inputs.  Results are
+ * identical; only speed changes.  Blocking. */
+int sdm_set_plan_limits(sdm_ctx *ctx, int32_t bucket_target, int32_t group_cap);
 
 /* ------------------------------------------------------------ R2 urand */
 /* u01[e] = U(seed, run, step, stream_id, e) for e in [0, n).

@@ -172,16 +172,16 @@ int sdm_read_errors(sdm_ctx *ctx, uint32_t *flags)
     SDM_CATCH
 }
 
-int sdm_set_plan_limits(sdm_ctx *ctx, int32_t bucket_cap, int32_t group_cap)
+int sdm_set_plan_limits(sdm_ctx *ctx, int32_t bucket_target, int32_t group_cap)
 {
     REQUIRE(ctx, "ctx is NULL");
-    REQUIRE(bucket_cap >= 0, "bucket_cap < 0");
+    REQUIRE(bucket_target >= 0, "bucket_target < 0");
     SDM_TRY
     SDM_HIP(hipDeviceSynchronize());
     for (auto &kv : ctx->plans)
         free_plan(kv.second);
     ctx->plans.clear();
-    ctx->dbg_bucket_cap = bucket_cap;
+    ctx->dbg_bucket_target = bucket_target;
     ctx->dbg_group_cap = group_cap;
     SDM_CATCH
 }

@@ -1,29 +1,31 @@
 // Bucketed segmented sort + pair pass: the fused SDM timestep on gfx950.
 //
 // Step 1 of the paper (Sec. 2.2, Sec. 3.2) orders each cell's live SDs by a
-// random key (the GPU strategy of the paper: a sort with random keys) and
-// pairs neighbours; Steps 2-3 evaluate eq. (3), gamma and eqs. (4)-(6) per
-// pair.  The data path here streams the state once:
+// random key (the GPU strategy the paper describes: a sort with random
+// keys) and pairs neighbours; Steps 2-3 evaluate eq. (3), gamma and
+// eqs. (4)-(6) per pair.  Three kernels:
 //
-//  k_scatter  (one pass over the SD slots, coalesced): liveness (Step 0:
-//             xi > 0), Philox shuffle key, bucket = (cell, top key bits);
-//             the record (key, s, xi, v) is appended to its bucket's region.
-//             Per-tile LDS histograms make one global atomic per
-//             (tile, bucket).  The last workgroup scans the bucket counts
-//             into ranks and cell_start.
-//  k_group    one workgroup per group of consecutive buckets: LDS counting
-//             sort by the next key bits, exact rank inside each sub-bucket
-//             by (key, s) comparisons, then idx, the pair probabilities,
-//             gamma and the collision update, written back only for pairs
-//             that collide.  Pairs that straddle two groups leave a seam
-//             record.
-//  k_seams    the straddling pairs, counters, and bookkeeping for the next
-//             launch.
+//  k_tile    one workgroup per tile of T SD slots (coalesced reads of xi and
+//            v): Step 0 liveness (xi > 0), Philox shuffle key, bucket =
+//            (cell, top key bits); an LDS counting sort by bucket, then the
+//            tile's records (key, s, xi, v) are written contiguously through
+//            LDS staging, with the tile's per-bucket offsets.  No global
+//            atomics except one per tile (live total) and one per (tile, big
+//            cell).
+//  k_group   one workgroup per group of consecutive buckets: gathers the
+//            group's run from every tile, obtains its rank offset by a
+//            decoupled look-back over the groups, sorts in LDS (counting
+//            sort by the next key bits, then exact ranks by (key, s) in each
+//            sub-bucket), writes idx, and evaluates the pairs: probability,
+//            gamma (one Philox block per two slots) and the collision update,
+//            written back only for pairs that collide.  A pair straddling
+//            two groups leaves a seam record.
+//  k_finish  the straddling pairs, the live count, and the per-launch
+//            bookkeeping (tickets, epoch).
 //
-// Oversized buckets (more records than their region) spill to an overflow
-// list and their group is sorted by a global-memory bitonic network instead
-// of in LDS; that path is exact, only slower, and practically never taken
-// for i.i.d. keys.
+// A group with more records than its LDS capacity is sorted in global
+// memory by a bitonic network instead (exact, only slower; for i.i.d. keys
+// practically never taken).
 #include <math.h>
 #include <stdio.h>
 
@@ -34,20 +36,39 @@
 
 namespace sdm {
 
-constexpr int SCATTER_THREADS = 1024;
-constexpr int SCATTER_EPT = 8;       // items per thread (even)
+constexpr int TILE_THREADS = 1024;
 constexpr int GROUP_THREADS = 512;
 constexpr int GROUP_EPT = 6;
-constexpr int GROUP_CAP = GROUP_THREADS * GROUP_EPT;
 constexpr int MAXB = 256;            // buckets per group
 constexpr int NSUB = 1024;           // sub-buckets per group
-constexpr int LDS_BINS_MAX = 16384;  // scatter histogram (64 KiB)
+constexpr int MAX_TILES = 1024;      // tiles per launch
+constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
+constexpr int TILE_LDS_BUDGET = 150 * 1024;
 constexpr double BUCKET_TARGET = 2048.0;
 constexpr double GROUP_TARGET = 2048.0;
-constexpr uint32_t NO_BUCKET = 0xFFFFFFFFu;
+constexpr uint32_t NO_BUCKET = 0xFFFFu;
+
+// look-back status word: kind (2 bits) | epoch (30 bits) | value (32 bits)
+constexpr uint64_t ST_AGG = 1ull, ST_PRE = 2ull;
+__device__ __forceinline__ uint64_t st_pack(uint64_t kind, uint32_t epoch, uint32_t v)
+{
+    return (kind << 62) | ((uint64_t)(epoch & 0x3FFFFFFFu) << 32) | v;
+}
+__device__ __forceinline__ uint64_t load64_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store64_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load32_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ------------------------------------------------------------------ args
-struct ScatterArgs {
+struct TileArgs {
     int mode;
     int64_t n_sd;
     const int64_t *n_live_in;
@@ -64,45 +85,44 @@ struct ScatterArgs {
     int key_shift;
     const int32_t *cell_h;
     const int32_t *cell_bucket_base;
-    const uint32_t *slot_base;
     int32_t B;
-    int32_t lds_bins;
     const uint32_t *seg_off;
     const int32_t *seg_run;
-    uint32_t *cursor;
+    const int32_t *big_cells;
+    int32_t n_big;
+    uint16_t *tile_off;
     uint64_t *rec_key;
     uint32_t *rec_s;
     uint64_t *rec_xi;
     double *rec_v;
-    uint32_t *ov_count;
-    uint64_t *ov_key;
-    uint32_t *ov_s;
-    uint32_t *ov_bucket;
-    uint32_t *rank_off;
-    uint32_t *cell_start;
-    int64_t *n_live_out;
-    uint32_t *ticket;
+    uint32_t *cell_tot;
+    uint32_t *n_acc;
     uint32_t *err;
 };
 
 struct GroupArgs {
     int mode;
+    int32_t B;
+    int32_t n_tiles;
+    int32_t tile;
+    int32_t n_cell;
     const int32_t *group_first;
     const int32_t *bucket_cell;
-    const uint32_t *slot_base;
     const uint8_t *sub_bits;
     const int32_t *cell_h;
-    uint32_t *cursor;
-    const uint32_t *rank_off;
-    const uint32_t *cell_start;
+    const int32_t *cell_bucket_base;
+    const uint8_t *cell_big;
+    const uint16_t *tile_off;
     const uint64_t *rec_key;
     const uint32_t *rec_s;
     const uint64_t *rec_xi;
     const double *rec_v;
-    const uint32_t *ov_count;
-    const uint64_t *ov_key;
-    const uint32_t *ov_s;
-    const uint32_t *ov_bucket;
+    const int32_t *cell_id;
+    const uint32_t *cell_tot;
+    uint32_t *n_acc;
+    uint64_t *gstat;
+    uint64_t *cstat;
+    uint32_t *cell_start;
     uint64_t *sk;
     uint32_t *ss;
     uint32_t *sb;
@@ -134,14 +154,14 @@ struct GroupArgs {
     uint32_t *group_tot;
 };
 
-struct SeamArgs {
+struct FinishArgs {
     int mode;
     int32_t G;
+    int32_t n_cell;
     const SeamRec *seam_open;
     const SeamRec *seam_close;
     const uint32_t *seam_state;
     const uint32_t *group_tot;
-    const uint32_t *cell_start;
     uint64_t *xi;
     double *attr;
     int32_t n_attr;
@@ -162,21 +182,20 @@ struct SeamArgs {
     int slot_cell_local;
     uint64_t *counters;
     double *gamma_out;
-    uint32_t *ov_count;
-    uint32_t *ticket;
+    const int32_t *big_cells;
+    int32_t n_big;
+    uint32_t *cell_tot;
+    uint32_t *n_acc;
+    uint32_t *cell_start;
+    int64_t *n_live_out;
     uint32_t *step_advance;
 };
 
 // --------------------------------------------------------------- helpers
-__device__ __forceinline__ uint32_t load_agent(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Segment (run) containing SD slot s: largest r with seg_off[r] <= s.
 __device__ __forceinline__ int find_seg(const uint32_t *seg_off, int n, uint32_t s)
 {
-    int lo = 0, hi = n;  // seg_off[n] > s
+    int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (seg_off[mid] <= s)
@@ -187,8 +206,21 @@ __device__ __forceinline__ int find_seg(const uint32_t *seg_off, int n, uint32_t
     return lo;
 }
 
-// Exclusive scan over THREADS values held one per thread; returns this
-// thread's exclusive prefix and the total in *total.
+// Largest i in [0, n) with tab[i] <= x (tab ascending, tab[0] <= x).
+__device__ __forceinline__ int upper_index(const uint32_t *tab, int n, uint32_t x)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Exclusive scan over THREADS values held one per thread.
 template <int THREADS>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *scratch,
                                                          uint32_t *total)
@@ -221,29 +253,58 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return res;
 }
 
-// ------------------------------------------------------------- k_scatter
-template <int THREADS, int EPT>
-__global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
+// In-place exclusive scan of an LDS array of n <= THREADS*PER entries;
+// arr[n] receives the total.
+template <int THREADS, int PER>
+__device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_t *scratch)
 {
-    extern __shared__ uint32_t hist[];
+    uint32_t loc[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x * PER + i;
+        loc[i] = idx < n ? arr[idx] : 0u;
+        sum += loc[i];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<THREADS>(sum, scratch, &total);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x * PER + i;
+        if (idx < n)
+            arr[idx] = run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 0)
+        arr[n] = total;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- k_tile
+template <int THREADS, int EPT, bool LIST>
+__global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
+{
+    constexpr int T = THREADS * EPT;
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t scan_scratch[THREADS / 64 + 1];
-    __shared__ int s_last;
+    const int B = a.B;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
+    const int hist_bytes = ((B + 1) * 4 + 15) & ~15;
+    uint64_t *stage = reinterpret_cast<uint64_t *>(smem + hist_bytes);
+    uint32_t *stage32 = reinterpret_cast<uint32_t *>(stage);
     const int tid = threadIdx.x;
-    for (int i = tid; i < a.lds_bins; i += THREADS)
+    for (int i = tid; i <= B; i += THREADS)
         hist[i] = 0;
     __syncthreads();
 
     const uint32_t step = step_of(a.step, a.step_dev);
-    const bool fused = a.mode == MODE_FUSED;
-    const int64_t n_items = fused ? a.n_sd : *a.n_live_in;
-    const bool lds = a.lds_bins > 0;
-    const int64_t pair0 = (int64_t)blockIdx.x * (THREADS * EPT / 2);
+    const int64_t n_items = LIST ? *a.n_live_in : a.n_sd;
+    const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
 
     uint64_t key[EPT];
     uint64_t xv[EPT];
-    uint32_t bk[EPT];
-    uint32_t rk[EPT];
-    uint32_t sid[EPT];
+    uint32_t bk[EPT];  // bucket (low 16 bits) | rank in tile (high 16 bits)
+    uint32_t sid[LIST ? EPT : 1];
 
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
@@ -253,7 +314,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
         bool live[2];
         int32_t cell[2];
         uint64_t x[2] = {0, 0};
-        if (fused) {
+        if (!LIST) {
             s[0] = (uint32_t)i0;
             s[1] = (uint32_t)(i0 + 1);
             if (i0 + 1 < n_items) {
@@ -271,12 +332,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
             s[0] = live[0] ? a.idx_in[i0] : 0;
             s[1] = live[1] ? a.idx_in[i0 + 1] : 0;
         }
-        // cells
         int seg = 0;
         if (a.seg_off) {
             seg = find_seg(a.seg_off, a.n_cell, s[0]);
             cell[0] = cell[1] = seg;
-            if (!fused)
+            if (LIST)
                 cell[1] = find_seg(a.seg_off, a.n_cell, s[1]);
         } else {
 #pragma unroll
@@ -290,7 +350,6 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
                 live[e] = false;
             }
         }
-        // shuffle keys
         uint64_t kk[2] = {0, 0};
         if (a.mode == MODE_CELLSORT) {
             kk[0] = (uint64_t)i0 << a.key_shift;
@@ -299,7 +358,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
 #pragma unroll
             for (int e = 0; e < 2; ++e)
                 kk[e] = live[e] ? uniform_to_key(a.u01[s[e]]) : 0;
-        } else if (fused) {
+        } else if (!LIST) {
             if (live[0] || live[1]) {
                 uint32_t run = a.run;
                 uint64_t lp = (uint64_t)p;
@@ -322,136 +381,175 @@ __global__ __launch_bounds__(THREADS) void k_scatter(ScatterArgs a)
             const int j = 2 * k + e;
             key[j] = kk[e];
             xv[j] = x[e];
-            sid[j] = s[e];
+            if (LIST)
+                sid[j] = s[e];
             bk[j] = NO_BUCKET;
-            rk[j] = 0;
             if (live[e]) {
                 const int h = a.cell_h[cell[e]];
                 const uint32_t b = (uint32_t)a.cell_bucket_base[cell[e]] +
                                    (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
-                bk[j] = b;
-                rk[j] = lds ? atomicAdd(&hist[b], 1u) : atomicAdd(&a.cursor[b], 1u);
+                const uint32_t r = atomicAdd(&hist[b], 1u);
+                bk[j] = b | (r << 16);
             }
         }
     }
     __syncthreads();
-    if (lds) {
-        for (int b = tid; b < a.B; b += THREADS) {
+    // exclusive bucket offsets of this tile
+    {
+        const int chunk = (B + THREADS - 1) / THREADS;
+        const int lo = min(B, tid * chunk), hi = min(B, lo + chunk);
+        uint32_t sum = 0;
+        for (int b = lo; b < hi; ++b)
+            sum += hist[b];
+        uint32_t total;
+        uint32_t run = block_exclusive_scan<THREADS>(sum, scan_scratch, &total);
+        for (int b = lo; b < hi; ++b) {
             const uint32_t c = hist[b];
-            if (c)
-                hist[b] = atomicAdd(&a.cursor[b], c);
+            hist[b] = run;
+            run += c;
+        }
+        if (tid == 0) {
+            hist[B] = total;
+            if (total)
+                atomicAdd(&a.n_acc[0], total);
         }
         __syncthreads();
     }
+    uint16_t *toff = a.tile_off + (int64_t)blockIdx.x * (B + 1);
+    for (int b = tid; b <= B; b += THREADS)
+        toff[b] = (uint16_t)hist[b];
+    for (int i = tid; i < a.n_big; i += THREADS) {
+        const int c = a.big_cells[i];
+        const uint32_t cnt = hist[a.cell_bucket_base[c + 1]] - hist[a.cell_bucket_base[c]];
+        if (cnt)
+            atomicAdd(&a.cell_tot[c], cnt);
+    }
+    const uint32_t total = hist[B];
+    uint32_t pos[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const uint32_t b = bk[j];
-        if (b == NO_BUCKET)
-            continue;
-        const uint32_t pos = (lds ? hist[b] : 0u) + rk[j];
-        const uint32_t base = a.slot_base[b];
-        const uint32_t cap = a.slot_base[b + 1] - base;
-        if (pos < cap) {
-            const uint32_t slot = base + pos;
-            a.rec_key[slot] = key[j];
-            a.rec_s[slot] = sid[j];
-            if (fused) {
-                a.rec_xi[slot] = xv[j];
-                a.rec_v[slot] = a.v[sid[j]];
-            }
-        } else {
-            const uint32_t o = atomicAdd(a.ov_count, 1u);
-            a.ov_key[o] = key[j];
-            a.ov_s[o] = sid[j];
-            a.ov_bucket[o] = b;
+        const uint32_t b = bk[j] & 0xFFFFu;
+        pos[j] = b == NO_BUCKET ? 0xFFFFFFFFu : hist[b] + (bk[j] >> 16);
+    }
+    // staged, coalesced write-out of the tile's records in bucket order
+    const int64_t rbase = (int64_t)blockIdx.x * T;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+        if (pos[j] != 0xFFFFFFFFu)
+            stage[pos[j]] = key[j];
+    __syncthreads();
+    for (uint32_t i = tid; i < total; i += THREADS)
+        a.rec_key[rbase + i] = stage[i];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (pos[j] != 0xFFFFFFFFu) {
+            uint32_t s;
+            if (LIST)
+                s = sid[j];
+            else
+                s = (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
+            stage32[pos[j]] = s;
         }
     }
-
-    // The last workgroup turns bucket counts into ranks and cell starts.
-    __threadfence();
     __syncthreads();
-    if (tid == 0)
-        s_last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last)
+    for (uint32_t i = tid; i < total; i += THREADS)
+        a.rec_s[rbase + i] = stage32[i];
+    if (LIST || a.mode != MODE_FUSED)
         return;
-    __threadfence();
-    const int B = a.B;
-    const int chunk = (B + THREADS - 1) / THREADS;
-    const int lo = min(B, tid * chunk), hi = min(B, lo + chunk);
-    uint32_t sum = 0;
-    for (int b = lo; b < hi; ++b)
-        sum += load_agent(&a.cursor[b]);
-    uint32_t total;
-    uint32_t run = block_exclusive_scan<THREADS>(sum, scan_scratch, &total);
-    for (int b = lo; b < hi; ++b) {
-        a.rank_off[b] = run;
-        run += load_agent(&a.cursor[b]);
-    }
-    if (tid == 0) {
-        a.rank_off[B] = total;
-        *a.n_live_out = (int64_t)total;
-        *a.ticket = 0;
-    }
-    __threadfence_block();
     __syncthreads();
-    for (int c = tid; c <= a.n_cell; c += THREADS)
-        a.cell_start[c] = a.rank_off[a.cell_bucket_base[c]];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+        if (pos[j] != 0xFFFFFFFFu)
+            stage[pos[j]] = xv[j];
+    __syncthreads();
+    for (uint32_t i = tid; i < total; i += THREADS)
+        a.rec_xi[rbase + i] = stage[i];
+    __syncthreads();
+    const double *vsrc = a.v;
+    double *stagev = reinterpret_cast<double *>(stage);
+#pragma unroll
+    for (int k = 0; k < EPT / 2; ++k) {
+        const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
+        double v0 = 0.0, v1 = 0.0;
+        if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
+            if (i0 + 1 < n_items) {
+                const double2 vv = *reinterpret_cast<const double2 *>(vsrc + i0);
+                v0 = vv.x;
+                v1 = vv.y;
+            } else {
+                v0 = vsrc[i0];
+            }
+        }
+        if (pos[2 * k] != 0xFFFFFFFFu)
+            stagev[pos[2 * k]] = v0;
+        if (pos[2 * k + 1] != 0xFFFFFFFFu)
+            stagev[pos[2 * k + 1]] = v1;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < total; i += THREADS)
+        a.rec_v[rbase + i] = stagev[i];
 }
 
 // ------------------------------------------------------- pair evaluation
-struct CellCtx {
-    int32_t c;
-    uint32_t cs, ce;
-};
-
-struct PairEnv {
-    const uint64_t *seg_dummy;
-};
-
-// Evaluates one pair (eq. 3, gamma, eqs. 4-6) and writes back on collision.
-template <class Args>
-__device__ __forceinline__ void do_pair(const Args &a, uint32_t step, int32_t c,
-                                        uint32_t cs, uint32_t ce, uint32_t r,
-                                        uint32_t sa, uint64_t xa, double va,
-                                        uint32_t sb_, uint64_t xb, double vb,
-                                        Stats &st)
-{
-    double dvc;
+struct PairCtx {
+    double norm;         // (dt / dV_c) * F(n_c)
     KernelDesc kd;
     uint32_t run;
-    uint32_t gbase = 0;
+    uint32_t slot_base;  // rank from which slots are numbered
+    uint32_t gbase;      // offset of the run's slots in gamma_out
+};
+
+template <class Args>
+__device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t cs, uint32_t n_c)
+{
+    PairCtx pc;
+    double dvc;
     if (a.seg_run) {
         dvc = a.seg_dv[c];
-        kd = a.kernels[a.seg_kernel[c]];
-        run = (uint32_t)a.seg_run[c];
-        gbase = a.seg_off[c] >> 1;
+        pc.kd = a.kernels[a.seg_kernel[c]];
+        pc.run = (uint32_t)a.seg_run[c];
+        pc.gbase = a.seg_off[c] >> 1;
     } else {
         dvc = a.dv_cell ? a.dv_cell[c] : a.dv;
-        kd = a.kern;
-        run = a.run;
+        pc.kd = a.kern;
+        pc.run = a.run;
+        pc.gbase = 0;
     }
-    const uint64_t n_c = (uint64_t)(ce - cs);
-    const double norm = (a.dt / dvc) * (double)pair_scale(n_c);
-    const double ak = kernel_value(kd, va, vb);
-    const uint64_t xm = xa > xb ? xa : xb;
-    const double p = (ak * (double)xm) * norm;
-    const uint32_t q = (r - (a.slot_cell_local ? cs : 0u)) >> 1;
-    const double phi = word_to_uniform(philox_word(a.seed, run, step, SDM_STREAM_GAMMA, q));
-    const double gamma = ceil(p - phi);
-    if (a.gamma_out)
-        a.gamma_out[gbase + q] = gamma;
-    const Collision col = collide(xa, xb, gamma, st);
-    if (col.g)
-        apply_collision(col, sa, sb_, a.xi, a.attr, a.n_attr, a.stride);
+    pc.norm = (a.dt / dvc) * (double)pair_scale((uint64_t)n_c);
+    pc.slot_base = a.slot_cell_local ? cs : 0u;
+    return pc;
 }
 
-// Output phase shared by the LDS and the global-memory paths: idx, pairs,
-// seam records.  Get provides s/xi/v of the element at local position f.
+// p of eq. (3) in the order kernel, times max xi, times (dt/dV) F(n).
+__device__ __forceinline__ double pair_prob(const PairCtx &pc, uint64_t xa, double va,
+                                            uint64_t xb, double vb)
+{
+    const double ak = kernel_value(pc.kd, va, vb);
+    const uint64_t xm = xa > xb ? xa : xb;
+    return (ak * (double)xm) * pc.norm;
+}
+
+template <class Args>
+__device__ __forceinline__ void finish_pair(const Args &a, const PairCtx &pc, uint32_t q,
+                                            double p, double phi, uint32_t sa, uint64_t xa,
+                                            uint32_t sbb, uint64_t xb, Stats &st)
+{
+    const double gamma = ceil(p - phi);
+    if (a.gamma_out)
+        a.gamma_out[pc.gbase + q] = gamma;
+    const Collision col = collide(xa, xb, gamma, st);
+    if (col.g)
+        apply_collision(col, sa, sbb, a.xi, a.attr, a.n_attr, a.stride);
+}
+
+// Output phase shared by the LDS and the global-memory paths.  Get gives
+// s / xi / v at local position f; t_* are the per-local-bucket tables.
 template <int THREADS, class Get>
 __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_t tot,
-                              uint32_t rank0, const uint32_t *t_off, const Get &get,
-                              uint32_t *red, uint32_t *s_state)
+                              uint32_t rank0, const uint32_t *t_off, const uint32_t *t_cs,
+                              const uint32_t *t_n, const Get &get, uint32_t *red,
+                              uint32_t *s_misc, uint32_t *opl)
 {
     const int tid = threadIdx.x;
     for (uint32_t f = tid; f < tot; f += THREADS)
@@ -460,56 +558,110 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
         return;
     const uint32_t step = step_of(a.step, a.step_dev);
     Stats st{0, 0, 0, 0, 0};
-    if (tid == 0)
-        *s_state = 0;
-    __syncthreads();
-    int bl = 0;
-    for (uint32_t f = tid; f < tot; f += THREADS) {
-        // bucket of f (t_off ascending, t_off[nb] = tot)
-        int lo = 0, hi = nb;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (t_off[mid] <= f)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        bl = lo;
-        const int32_t c = a.bucket_cell[b0 + bl];
-        const uint32_t cs = a.cell_start[c], ce = a.cell_start[c + 1];
+    // 1. openers with a local partner -> compact list (contiguous chunks)
+    const uint32_t per = (tot + THREADS - 1) / THREADS;
+    const uint32_t f0 = min(tot, tid * per), f1 = min(tot, f0 + per);
+    uint32_t cnt = 0;
+    uint32_t state = 0;
+    for (uint32_t f = f0; f < f1; ++f) {
+        const int bl = upper_index(t_off, nb, f);
         const uint32_t r = rank0 + f;
+        const uint32_t cs = t_cs[bl], ce = cs + t_n[bl];
         const uint32_t ic = r - cs;
         const bool opener = ((ic & 1u) == 0u) && (r + 1 < ce);
-        if (opener) {
-            if (f + 1 < tot) {
-                do_pair(a, step, c, cs, ce, r, get.s(f), get.xi(f), get.v(f),
-                        get.s(f + 1), get.xi(f + 1), get.v(f + 1), st);
-            } else {
-                SeamRec rec;
-                rec.xi = get.xi(f);
-                rec.v = get.v(f);
-                rec.s = get.s(f);
-                rec.rank = r;
-                rec.cell = c;
-                rec.pad = 0;
-                a.seam_open[g] = rec;
-                atomicOr(s_state, 1u);
-            }
-        } else if (f == 0 && (ic & 1u)) {
+        if (opener && f + 1 < tot) {
+            ++cnt;
+        } else if (opener || (f == 0 && (ic & 1u))) {
             SeamRec rec;
             rec.xi = get.xi(f);
             rec.v = get.v(f);
             rec.s = get.s(f);
             rec.rank = r;
-            rec.cell = c;
+            rec.cell = a.bucket_cell[b0 + bl];
+            rec.cs = cs;
+            rec.n_c = t_n[bl];
             rec.pad = 0;
-            a.seam_close[g] = rec;
-            atomicOr(s_state, 2u);
+            if (opener) {
+                a.seam_open[g] = rec;
+                state |= 1u;
+            } else {
+                a.seam_close[g] = rec;
+                state |= 2u;
+            }
         }
+    }
+    if (state)
+        atomicOr(&s_misc[2], state);
+    uint32_t n_op;
+    uint32_t w = block_exclusive_scan<THREADS>(cnt, red, &n_op);
+    for (uint32_t f = f0; f < f1 && cnt; ++f) {
+        const int bl = upper_index(t_off, nb, f);
+        const uint32_t r = rank0 + f;
+        const uint32_t cs = t_cs[bl], ce = cs + t_n[bl];
+        const uint32_t ic = r - cs;
+        if (((ic & 1u) == 0u) && (r + 1 < ce) && f + 1 < tot)
+            opl[w++] = f;
+    }
+    __syncthreads();
+    // 2. pairs, two consecutive openers per thread so that slots 2u, 2u+1
+    //    share one Philox block when they are adjacent
+    uint32_t shift = 0;
+    if (n_op) {
+        const uint32_t fa = opl[0];
+        const int bl = upper_index(t_off, nb, fa);
+        const uint32_t base = a.slot_cell_local ? t_cs[bl] : 0u;
+        shift = ((rank0 + fa - base) >> 1) & 1u;
+    }
+    for (uint32_t j = tid; 2 * j < n_op + shift; j += THREADS) {
+        const int k0 = (int)(2 * j) - (int)shift;
+        uint32_t qv[2] = {0, 0};
+        double pv[2] = {0.0, 0.0};
+        PairCtx pcv[2];
+        uint32_t sa[2] = {0, 0}, sb_[2] = {0, 0};
+        uint64_t xa[2] = {0, 0}, xb[2] = {0, 0};
+        bool valid[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = k0 + u;
+            valid[u] = k >= 0 && k < (int)n_op;
+            if (!valid[u])
+                continue;
+            const uint32_t f = opl[k];
+            const int bl = upper_index(t_off, nb, f);
+            const int32_t c = a.bucket_cell[b0 + bl];
+            pcv[u] = pair_ctx(a, c, t_cs[bl], t_n[bl]);
+            const uint32_t r = rank0 + f;
+            qv[u] = (r - pcv[u].slot_base) >> 1;
+            sa[u] = get.s(f);
+            xa[u] = get.xi(f);
+            const double va = get.v(f);
+            sb_[u] = get.s(f + 1);
+            xb[u] = get.xi(f + 1);
+            const double vb = get.v(f + 1);
+            pv[u] = pair_prob(pcv[u], xa[u], va, xb[u], vb);
+        }
+        double phi[2] = {0.0, 0.0};
+        if (valid[0] && valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1 &&
+            pcv[0].run == pcv[1].run) {
+            const WordPair wp = philox_words(a.seed, pcv[0].run, step, SDM_STREAM_GAMMA,
+                                             qv[0] >> 1);
+            phi[0] = word_to_uniform(wp.even);
+            phi[1] = word_to_uniform(wp.odd);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (valid[u])
+                    phi[u] = word_to_uniform(
+                        philox_word(a.seed, pcv[u].run, step, SDM_STREAM_GAMMA, qv[u]));
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (valid[u])
+                finish_pair(a, pcv[u], qv[u], pv[u], phi[u], sa[u], xa[u], sb_[u], xb[u], st);
     }
     flush_stats<THREADS>(st, a.counters, red);
     if (tid == 0) {
-        a.seam_state[g] = *s_state;
+        a.seam_state[g] = s_misc[2];
         a.group_tot[g] = tot;
     }
 }
@@ -542,64 +694,154 @@ __device__ __forceinline__ bool rec_less(uint32_t ba, uint64_t ka, uint32_t sa,
     return sa < sbb;
 }
 
+// Local bucket of a record of this group.
+__device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int nb, uint64_t key,
+                                                 uint32_t s)
+{
+    if (nb == 1)
+        return 0;
+    int c = 0;
+    if (a.seg_off)
+        c = find_seg(a.seg_off, a.n_cell, s);
+    else if (a.cell_id)
+        c = a.cell_id[s];
+    const int h = a.cell_h[c];
+    const uint32_t b = (uint32_t)a.cell_bucket_base[c] + (h ? (uint32_t)(key >> (53 - h)) : 0u);
+    return b - (uint32_t)b0;
+}
+
 // --------------------------------------------------------------- k_group
 template <int THREADS, int EPT>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
+    __shared__ uint32_t run_pre[MAX_TILES + 1];
+    __shared__ uint16_t run_lo[MAX_TILES];
     __shared__ uint32_t t_off[MAXB + 1];
     __shared__ uint32_t t_cnt[MAXB];
     __shared__ uint32_t t_subbase[MAXB + 1];
     __shared__ uint32_t t_shift[MAXB];
     __shared__ uint32_t t_mask[MAXB];
-    __shared__ uint32_t sub_hist[NSUB + 1];
+    __shared__ uint32_t t_cs[MAXB];
+    __shared__ uint32_t t_n[MAXB];
+    // sub-bucket histogram during the sort, opener list afterwards
+    __shared__ uint32_t sub_hist[(NSUB + 1) > (CAP / 2 + 1) ? (NSUB + 1) : (CAP / 2 + 1)];
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];
-    __shared__ uint32_t s_misc[4];
+    __shared__ uint32_t s_misc[8];
     __shared__ __align__(16) unsigned char pool[CAP * 20];
 
     const int tid = threadIdx.x;
-    const int g = blockIdx.x;
+    if (tid == 0) {
+        s_misc[0] = atomicAdd(&a.n_acc[1], 1u);  // logical group id
+        s_misc[1] = load32_agent(&a.n_acc[2]);   // epoch
+        s_misc[2] = 0;
+    }
+    __syncthreads();
+    const int g = (int)s_misc[0];
+    const uint32_t epoch = s_misc[1];
     const int b0 = a.group_first[g], b1 = a.group_first[g + 1];
     const int nb = b1 - b0;
+    const int nt = a.n_tiles;
+    const int64_t Bp = a.B + 1;
+
+    // this group's run in every tile
+    for (int t = tid; t < nt; t += THREADS) {
+        const uint32_t lo = a.tile_off[t * Bp + b0];
+        const uint32_t hi = a.tile_off[t * Bp + b1];
+        run_lo[t] = (uint16_t)lo;
+        run_pre[t] = hi - lo;
+    }
     for (int i = tid; i < nb; i += THREADS) {
         const int b = b0 + i;
-        t_cnt[i] = a.cursor[b];
         const int h = a.cell_h[a.bucket_cell[b]];
         const int u = a.sub_bits[b];
         t_shift[i] = (uint32_t)(53 - h - u);
         t_mask[i] = (1u << u) - 1u;
-        t_subbase[i] = 1u << u;  // count, scanned below
+        t_subbase[i] = 1u << u;
+        if (nb > 1) {
+            uint32_t c = 0;
+            for (int t = 0; t < nt; ++t)
+                c += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
+            t_cnt[i] = c;
+        }
     }
     __syncthreads();
+    lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, nt, red);
+    const uint32_t tot = run_pre[nt];
     if (tid == 0) {
-        uint32_t off = 0, sub = 0, ovf = 0;
+        if (nb == 1)
+            t_cnt[0] = tot;
+        // decoupled look-back over the groups for this group's first rank
+        store64_agent(&a.gstat[g], st_pack(g == 0 ? ST_PRE : ST_AGG, epoch, tot));
+        uint32_t prefix = 0;
+        if (g > 0) {
+            int j = g - 1;
+            while (true) {
+                const uint64_t w = load64_agent(&a.gstat[j]);
+                const uint32_t we = (uint32_t)(w >> 32) & 0x3FFFFFFFu;
+                const uint64_t kind = w >> 62;
+                if (kind == 0 || we != (epoch & 0x3FFFFFFFu))
+                    continue;
+                prefix += (uint32_t)w;
+                if (kind == ST_PRE)
+                    break;
+                --j;
+            }
+            store64_agent(&a.gstat[g], st_pack(ST_PRE, epoch, prefix + tot));
+        }
+        s_misc[3] = prefix;
+        uint32_t off = 0, sub = 0;
         for (int i = 0; i < nb; ++i) {
-            const uint32_t c = t_cnt[i];
-            const uint32_t cap = a.slot_base[b0 + i + 1] - a.slot_base[b0 + i];
-            if (c > cap)
-                ovf = 1;
             t_off[i] = off;
-            off += c;
+            off += t_cnt[i];
             const uint32_t ns = t_subbase[i];
             t_subbase[i] = sub;
             sub += ns;
         }
         t_off[nb] = off;
         t_subbase[nb] = sub;
-        s_misc[0] = off;
-        s_misc[1] = ovf;
+        // start rank of a big cell that began in an earlier group
+        const int c0 = a.bucket_cell[b0];
+        if (a.cell_bucket_base[c0] < b0) {
+            uint64_t w;
+            do {
+                w = load64_agent(&a.cstat[c0]);
+            } while ((uint32_t)(w >> 32) != epoch + 1u);
+            s_misc[4] = (uint32_t)w;
+        }
     }
     __syncthreads();
-    const uint32_t tot = s_misc[0];
-    const bool ovf = s_misc[1] != 0;
-    const uint32_t rank0 = a.rank_off[b0];
-    // reset the bucket cursors for the next launch (counts are in LDS)
-    for (int i = tid; i < nb; i += THREADS)
-        a.cursor[b0 + i] = 0;
-    const uint32_t cap_here = a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
+    const uint32_t rank0 = s_misc[3];
+    // per-local-bucket cell start and cell size
+    for (int i = tid; i < nb; i += THREADS) {
+        const int b = b0 + i;
+        const int c = a.bucket_cell[b];
+        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
+        uint32_t cs;
+        if (first >= b0) {
+            cs = rank0 + t_off[first - b0];
+            if (b == first) {
+                a.cell_start[c] = cs;
+                if (a.cell_big[c])
+                    store64_agent(&a.cstat[c], ((uint64_t)(epoch + 1u) << 32) | cs);
+            }
+        } else {
+            cs = s_misc[4];
+        }
+        uint32_t n_c;
+        if (a.cell_big[c])
+            n_c = load32_agent(&a.cell_tot[c]);
+        else
+            n_c = t_off[last - b0] - t_off[first - b0];
+        t_cs[i] = cs;
+        t_n[i] = n_c;
+    }
+    __syncthreads();
+    const uint32_t cap_here =
+        a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
     const bool fused = a.mode == MODE_FUSED;
 
-    if (tot <= cap_here && !ovf) {
+    if (tot <= cap_here) {
         // ------------------------------------------------ LDS path
         uint64_t *K1 = reinterpret_cast<uint64_t *>(pool);
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
@@ -616,59 +858,30 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
-            sbk[e] = NO_BUCKET;
+            sbk[e] = 0xFFFFFFFFu;
             if (li < tot) {
-                int lo = 0, hi = nb;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (t_off[mid] <= li)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                const uint32_t slot = a.slot_base[b0 + lo] + (li - t_off[lo]);
-                key[e] = a.rec_key[slot];
-                sid[e] = a.rec_s[slot];
+                const int t = upper_index(run_pre, nt, li);
+                const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
+                key[e] = a.rec_key[pos];
+                sid[e] = a.rec_s[pos];
                 if (fused) {
-                    xv[e] = a.rec_xi[slot];
-                    vv[e] = a.rec_v[slot];
+                    xv[e] = a.rec_xi[pos];
+                    vv[e] = a.rec_v[pos];
                 } else {
                     xv[e] = 0;
                     vv[e] = 0.0;
                 }
-                const uint32_t sub = (uint32_t)(key[e] >> t_shift[lo]) & t_mask[lo];
-                sbk[e] = t_subbase[lo] + sub;
+                const uint32_t bl = local_bucket(a, b0, nb, key[e], sid[e]);
+                const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
+                sbk[e] = t_subbase[bl] + sub;
                 lrk[e] = atomicAdd(&sub_hist[sbk[e]], 1u);
             }
         }
         __syncthreads();
-        // exclusive scan of the sub-bucket histogram (nsub <= NSUB)
-        {
-            constexpr int PER = (NSUB + THREADS - 1) / THREADS;
-            uint32_t loc[PER];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const uint32_t idx = tid * PER + i;
-                loc[i] = idx < nsub ? sub_hist[idx] : 0u;
-                sum += loc[i];
-            }
-            uint32_t total;
-            uint32_t run = block_exclusive_scan<THREADS>(sum, red, &total);
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const uint32_t idx = tid * PER + i;
-                if (idx < nsub)
-                    sub_hist[idx] = run;
-                run += loc[i];
-            }
-            if (tid == 0)
-                sub_hist[nsub] = total;
-        }
-        __syncthreads();
+        lds_exclusive_scan<THREADS, (NSUB + THREADS - 1) / THREADS>(sub_hist, (int)nsub, red);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (sbk[e] != NO_BUCKET) {
+            if (sbk[e] != 0xFFFFFFFFu) {
                 const uint32_t pos = sub_hist[sbk[e]] + lrk[e];
                 K1[pos] = key[e];
                 S1[pos] = sid[e];
@@ -677,7 +890,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             }
         }
         __syncthreads();
-        // exact rank inside each sub-bucket by (key, s)
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t pos = (uint32_t)(e * THREADS + tid);
@@ -698,7 +910,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         uint32_t fp[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
-            if (sbk[e] != NO_BUCKET)
+            if (sbk[e] != 0xFFFFFFFFu)
                 fp[e] = FP[e * THREADS + tid];
         __syncthreads();
         uint64_t *XF = reinterpret_cast<uint64_t *>(pool);
@@ -706,7 +918,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         uint32_t *SF = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (sbk[e] != NO_BUCKET) {
+            if (sbk[e] != 0xFFFFFFFFu) {
                 XF[fp[e]] = xv[e];
                 VF[fp[e]] = vv[e];
                 SF[fp[e]] = sid[e];
@@ -714,51 +926,32 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
         __syncthreads();
         LdsGet get{SF, XF, VF};
-        group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, get, red, &s_misc[2]);
+        // the opener list reuses the sub-bucket histogram (dead after ranking)
+        group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, t_cs, t_n, get, red, s_misc,
+                               sub_hist);
         return;
     }
 
     // ---------------------------------------------------- global path
-    // Gather the group's records (bucket regions + overflow list) into
-    // scratch at [2 rank0, 2 rank0 + P), P = next power of two >= tot, and
-    // sort them there by (bucket, key, s) with a bitonic network.  The
-    // ranges of consecutive groups are disjoint because P <= 2 tot.
-    if (tot == 0) {
-        GlobalGet none{a.ss, nullptr, nullptr};
-        group_outputs<THREADS>(a, g, b0, nb, 0, rank0, t_off, none, red, &s_misc[2]);
-        return;
-    }
+    // The group's records are gathered into scratch at [2 rank0, 2 rank0 + P),
+    // P = next power of two >= tot (ranges of consecutive groups are disjoint
+    // since P <= 2 tot), and sorted there by (bucket, key, s) with a bitonic
+    // network.  The pair phase then reads xi and v from the state; its
+    // opener list lives in scratch too (at 2 rank0 + P .. in the ss array of
+    // the next half), so any group size is handled.
     const uint32_t base2 = 2u * rank0;
     uint32_t P = 1;
     while (P < tot)
         P <<= 1;
-    if (tid == 0)
-        s_misc[3] = 0;
-    __syncthreads();
-    for (int i = 0; i < nb; ++i) {
-        const uint32_t cap = a.slot_base[b0 + i + 1] - a.slot_base[b0 + i];
-        const uint32_t m = min(t_cnt[i], cap);
-        for (uint32_t j = tid; j < m; j += THREADS) {
-            const uint32_t slot = a.slot_base[b0 + i] + j;
-            const uint32_t pos = atomicAdd(&s_misc[3], 1u);
-            a.sk[base2 + pos] = a.rec_key[slot];
-            a.ss[base2 + pos] = a.rec_s[slot];
-            a.sb[base2 + pos] = (uint32_t)i;
-        }
+    for (uint32_t li = tid; li < tot; li += THREADS) {
+        const int t = upper_index(run_pre, nt, li);
+        const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
+        const uint64_t k = a.rec_key[pos];
+        const uint32_t s = a.rec_s[pos];
+        a.sk[base2 + li] = k;
+        a.ss[base2 + li] = s;
+        a.sb[base2 + li] = local_bucket(a, b0, nb, k, s);
     }
-    if (ovf) {
-        const uint32_t n_ov = *a.ov_count;
-        for (uint32_t i = tid; i < n_ov; i += THREADS) {
-            const uint32_t b = a.ov_bucket[i];
-            if (b >= (uint32_t)b0 && b < (uint32_t)b1) {
-                const uint32_t pos = atomicAdd(&s_misc[3], 1u);
-                a.sk[base2 + pos] = a.ov_key[i];
-                a.ss[base2 + pos] = a.ov_s[i];
-                a.sb[base2 + pos] = b - (uint32_t)b0;
-            }
-        }
-    }
-    __syncthreads();
     for (uint32_t i = tot + tid; i < P; i += THREADS) {
         a.sk[base2 + i] = ~0ull;
         a.ss[base2 + i] = ~0u;
@@ -791,12 +984,14 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
     }
     GlobalGet get{a.ss + base2, fused ? a.xi : nullptr, fused ? a.attr : nullptr};
-    group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, get, red, &s_misc[2]);
+    // opener list in the (now free) bucket scratch of this group
+    group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, t_cs, t_n, get, red, s_misc,
+                           a.sb + base2);
 }
 
-// --------------------------------------------------------------- k_seams
+// -------------------------------------------------------------- k_finish
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_seams(SeamArgs a)
+__global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
 {
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];
     __shared__ int s_last;
@@ -810,25 +1005,37 @@ __global__ __launch_bounds__(THREADS) void k_seams(SeamArgs a)
             ++g2;
         if (g2 < a.G) {
             const SeamRec cl = a.seam_close[g2];
-            const uint32_t cs = a.cell_start[op.cell], ce = a.cell_start[op.cell + 1];
-            do_pair(a, step, op.cell, cs, ce, op.rank, op.s, op.xi, op.v, cl.s, cl.xi,
-                    cl.v, st);
+            const PairCtx pc = pair_ctx(a, op.cell, op.cs, op.n_c);
+            const uint32_t q = (op.rank - pc.slot_base) >> 1;
+            const double p = pair_prob(pc, op.xi, op.v, cl.xi, cl.v);
+            const double phi =
+                word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
+            finish_pair(a, pc, q, p, phi, op.s, op.xi, cl.s, cl.xi, st);
         }
     }
     if (a.mode == MODE_FUSED)
         flush_stats<THREADS>(st, a.counters, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *a.ov_count = 0;
-    // the last workgroup advances the device step counter
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < a.n_big; i += THREADS)
+            a.cell_tot[a.big_cells[i]] = 0;
+        if (threadIdx.x == 0) {
+            const uint32_t n = a.n_acc[0];
+            *a.n_live_out = (int64_t)n;
+            a.cell_start[a.n_cell] = n;
+            a.n_acc[0] = 0;
+            a.n_acc[1] = 0;
+            a.n_acc[2] = (a.n_acc[2] + 1u) & 0x3FFFFFFFu;
+        }
+    }
     if (a.step_advance) {
         __threadfence();
         __syncthreads();
         if (threadIdx.x == 0)
-            s_last = atomicAdd(a.ticket, 1u) == gridDim.x - 1;
+            s_last = atomicAdd(&a.n_acc[3], 1u) == gridDim.x - 1;
         __syncthreads();
         if (s_last && threadIdx.x == 0) {
             *a.step_advance = *a.step_advance + 1u;
-            *a.ticket = 0;
+            a.n_acc[3] = 0;
         }
     }
 }
@@ -872,42 +1079,40 @@ static int ceil_log2_u64(uint64_t x)
     return b;
 }
 
-// Describes one cell (or run) for plan building.
-struct CellPlanIn {
-    double expected;  // expected live SDs
-};
+static int tile_ept_for(int B)
+{
+    const int hist = ((B + 1) * 4 + 15) & ~15;
+    for (int ept : {16, 8, 4}) {
+        if (hist + TILE_THREADS * ept * 8 <= TILE_LDS_BUDGET)
+            return ept;
+    }
+    return 0;
+}
 
 static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
-                        const std::vector<double> &expected, bool batched)
+                        const std::vector<double> &expected)
 {
     Plan *p = new Plan();
     try {
         const int32_t C = (int32_t)expected.size();
+        const double target = ctx->dbg_bucket_target > 0 ? (double)ctx->dbg_bucket_target
+                                                          : BUCKET_TARGET;
         p->mode = mode;
         p->n_items = n_items;
         p->n_cell = C;
         std::vector<int32_t> cell_h(C), cell_bb(C + 1);
         std::vector<int32_t> bucket_cell;
-        std::vector<uint32_t> slot_base;
         std::vector<uint8_t> sub_bits;
         std::vector<double> bucket_exp;
-        uint64_t slots = 0;
         int32_t B = 0;
         for (int32_t c = 0; c < C; ++c) {
             const double m = std::max(expected[c], 1.0);
             int h = 0;
-            if (mode != MODE_CELLSORT || true) {
-                while (m / std::ldexp(1.0, h) > BUCKET_TARGET && h < 24)
-                    ++h;
-            }
+            while (m / std::ldexp(1.0, h) > target && h < 20)
+                ++h;
             cell_h[c] = h;
             cell_bb[c] = B;
             const double e = m / std::ldexp(1.0, h);
-            uint32_t cap;
-            if (ctx->dbg_bucket_cap > 0)
-                cap = (uint32_t)ctx->dbg_bucket_cap;
-            else
-                cap = (uint32_t)(std::ceil((e + 10.0 * std::sqrt(e) + 64.0) / 64.0) * 64.0);
             int u = 0;
             while (e / std::ldexp(1.0, u + 1) >= 4.0 && u < 10)
                 ++u;
@@ -915,19 +1120,16 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                 u = 53 - h;
             for (int i = 0; i < (1 << h); ++i) {
                 bucket_cell.push_back(c);
-                slot_base.push_back((uint32_t)slots);
                 sub_bits.push_back((uint8_t)u);
                 bucket_exp.push_back(e);
-                slots += cap;
                 ++B;
+                if (B > MAX_B)
+                    throw HipError{hipErrorInvalidValue, "too many buckets for one plan"};
             }
         }
         cell_bb[C] = B;
-        slot_base.push_back((uint32_t)slots);
-        if (slots >= 0xFFFFFFF0ull)
-            throw HipError{hipErrorOutOfMemory, "plan too large"};
         // groups: consecutive buckets with expected total <= GROUP_TARGET
-        std::vector<int32_t> group_first;
+        std::vector<int32_t> group_first, group_of_bucket(B);
         {
             int32_t b = 0;
             while (b < B) {
@@ -941,38 +1143,54 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                         break;
                     acc += bucket_exp[b];
                     nsub += ns;
+                    group_of_bucket[b] = (int32_t)group_first.size() - 1;
                     ++n;
                     ++b;
                 }
             }
             group_first.push_back(B);
         }
+        std::vector<uint8_t> cell_big(C, 0);
+        std::vector<int32_t> big_cells;
+        for (int32_t c = 0; c < C; ++c) {
+            if (cell_bb[c + 1] > cell_bb[c] &&
+                group_of_bucket[cell_bb[c]] != group_of_bucket[cell_bb[c + 1] - 1]) {
+                cell_big[c] = 1;
+                big_cells.push_back(c);
+            }
+        }
+        const int ept = tile_ept_for(B);
+        if (ept == 0)
+            throw HipError{hipErrorInvalidValue, "bucket table exceeds the tile LDS budget"};
+        p->tile = TILE_THREADS * ept;
+        p->n_tiles = (int32_t)std::max<int64_t>(1, (n_items + p->tile - 1) / p->tile);
+        if (p->n_tiles > MAX_TILES)
+            throw HipError{hipErrorInvalidValue, "too many SD slots for one plan"};
         p->B = B;
         p->G = (int32_t)group_first.size() - 1;
-        p->S = (uint32_t)slots;
-        p->lds_bins = B <= LDS_BINS_MAX ? B : 0;
+        p->n_big = (int32_t)big_cells.size();
         p->cell_h = upload(p, cell_h);
         p->cell_bucket_base = upload(p, cell_bb);
+        p->cell_big = upload(p, cell_big);
+        p->big_cells = upload(p, big_cells);
         p->bucket_cell = upload(p, bucket_cell);
-        p->slot_base = upload(p, slot_base);
         p->sub_bits = upload(p, sub_bits);
         p->group_first = upload(p, group_first);
         const bool fused = mode == MODE_FUSED;
-        p->cursor = (uint32_t *)dalloc(p, 4ull * B);
-        p->rank_off = (uint32_t *)dalloc(p, 4ull * (B + 1));
+        const size_t R = (size_t)p->n_tiles * p->tile;
+        p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
+        p->rec_key = (uint64_t *)dalloc(p, 8ull * R);
+        p->rec_s = (uint32_t *)dalloc(p, 4ull * R);
+        if (fused) {
+            p->rec_xi = (uint64_t *)dalloc(p, 8ull * R);
+            p->rec_v = (double *)dalloc(p, 8ull * R);
+        }
+        p->cell_tot = (uint32_t *)dalloc(p, 4ull * C);
+        p->n_acc = (uint32_t *)dalloc(p, 64);
+        p->gstat = (uint64_t *)dalloc(p, 8ull * p->G);
+        p->cstat = (uint64_t *)dalloc(p, 8ull * C);
         p->cell_start_ws = (uint32_t *)dalloc(p, 4ull * (C + 1));
         p->n_live_ws = (int64_t *)dalloc(p, 8);
-        p->ticket = (uint32_t *)dalloc(p, 16);
-        p->rec_key = (uint64_t *)dalloc(p, 8ull * slots);
-        p->rec_s = (uint32_t *)dalloc(p, 4ull * slots);
-        if (fused) {
-            p->rec_xi = (uint64_t *)dalloc(p, 8ull * slots);
-            p->rec_v = (double *)dalloc(p, 8ull * slots);
-        }
-        p->ov_count = (uint32_t *)dalloc(p, 16);
-        p->ov_key = (uint64_t *)dalloc(p, 8ull * n_items + 8);
-        p->ov_s = (uint32_t *)dalloc(p, 4ull * n_items + 8);
-        p->ov_bucket = (uint32_t *)dalloc(p, 4ull * n_items + 8);
         p->sk = (uint64_t *)dalloc(p, 16ull * n_items + 64);
         p->ss = (uint32_t *)dalloc(p, 8ull * n_items + 64);
         p->sb = (uint32_t *)dalloc(p, 8ull * n_items + 64);
@@ -980,13 +1198,13 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->seam_close = (SeamRec *)dalloc(p, sizeof(SeamRec) * p->G);
         p->seam_state = (uint32_t *)dalloc(p, 4ull * p->G);
         p->group_tot = (uint32_t *)dalloc(p, 4ull * p->G);
-        SDM_HIP(hipMemset(p->cursor, 0, 4ull * B));
-        SDM_HIP(hipMemset(p->ticket, 0, 16));
-        SDM_HIP(hipMemset(p->ov_count, 0, 16));
+        SDM_HIP(hipMemset(p->cell_tot, 0, 4ull * C));
+        SDM_HIP(hipMemset(p->n_acc, 0, 64));
+        SDM_HIP(hipMemset(p->gstat, 0, 8ull * p->G));
+        SDM_HIP(hipMemset(p->cstat, 0, 8ull * C));
         SDM_HIP(hipMemset(p->seam_state, 0, 4ull * p->G));
         SDM_HIP(hipMemset(p->group_tot, 0, 4ull * p->G));
         SDM_HIP(hipDeviceSynchronize());
-        (void)batched;
     } catch (...) {
         free_plan(p);
         throw;
@@ -1004,95 +1222,108 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
     if (it != ctx->plans.end())
         return it->second;
     std::vector<double> exp(n_cell, expected_per_cell);
-    Plan *p = build_plan(ctx, mode, n_items, exp, false);
+    Plan *p = build_plan(ctx, mode, n_items, exp);
     ctx->plans[key] = p;
     return p;
 }
 
-static void set_kernel_attributes()
+template <int EPT, bool LIST>
+static void launch_tile(int grid, size_t lds, hipStream_t stream, const TileArgs &ta)
 {
-    static bool done = false;
-    if (done)
-        return;
-    SDM_HIP(hipFuncSetAttribute((const void *)k_scatter<SCATTER_THREADS, SCATTER_EPT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                LDS_BINS_MAX * 4 + 1024));
-    done = true;
+    static bool attr_set = false;
+    if (!attr_set) {
+        SDM_HIP(hipFuncSetAttribute((const void *)k_tile<TILE_THREADS, EPT, LIST>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    TILE_LDS_BUDGET));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tile<TILE_THREADS, EPT, LIST>), dim3(grid), dim3(TILE_THREADS), lds,
+                       stream, ta);
 }
 
 void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
 {
-    set_kernel_attributes();
-    const bool fused = p->mode == MODE_FUSED;
+    const bool list = p->mode != MODE_FUSED;
     uint32_t *cell_start = in.cell_start ? in.cell_start : p->cell_start_ws;
     int64_t *n_live_out = in.n_live_out ? in.n_live_out : p->n_live_ws;
-
-    ScatterArgs sa{};
-    sa.mode = p->mode;
-    sa.n_sd = in.n_sd;
-    sa.n_live_in = in.n_live_in;
-    sa.idx_in = in.idx_in;
-    sa.xi = in.xi;
-    sa.v = in.attr;
-    sa.cell_id = in.cell_id;
-    sa.n_cell = p->n_cell;
-    sa.u01 = in.u01;
-    sa.seed = in.seed;
-    sa.run = in.run;
-    sa.step = in.step;
-    sa.step_dev = in.step_dev;
-    sa.key_shift = 53 - std::max(1, ceil_log2_u64((uint64_t)std::max<int64_t>(p->n_items, 2)));
-    sa.cell_h = p->cell_h;
-    sa.cell_bucket_base = p->cell_bucket_base;
-    sa.slot_base = p->slot_base;
-    sa.B = p->B;
-    sa.lds_bins = p->lds_bins;
-    sa.seg_off = p->seg_off;
-    sa.seg_run = p->seg_run;
-    sa.cursor = p->cursor;
-    sa.rec_key = p->rec_key;
-    sa.rec_s = p->rec_s;
-    sa.rec_xi = p->rec_xi;
-    sa.rec_v = p->rec_v;
-    sa.ov_count = p->ov_count;
-    sa.ov_key = p->ov_key;
-    sa.ov_s = p->ov_s;
-    sa.ov_bucket = p->ov_bucket;
-    sa.rank_off = p->rank_off;
-    sa.cell_start = cell_start;
-    sa.n_live_out = n_live_out;
-    sa.ticket = p->ticket;
-    sa.err = ctx->err_dev;
     auto mark = [&](int i) {
         if (in.events[i])
             SDM_HIP(hipEventRecord(in.events[i], stream));
     };
-    const int64_t items = fused ? in.n_sd : p->n_items;
-    const int64_t per_block = (int64_t)SCATTER_THREADS * SCATTER_EPT;
-    const int grid1 = (int)std::max<int64_t>(1, (items + per_block - 1) / per_block);
+
+    TileArgs ta{};
+    ta.mode = p->mode;
+    ta.n_sd = in.n_sd;
+    ta.n_live_in = in.n_live_in;
+    ta.idx_in = in.idx_in;
+    ta.xi = in.xi;
+    ta.v = in.attr;
+    ta.cell_id = in.cell_id;
+    ta.n_cell = p->n_cell;
+    ta.u01 = in.u01;
+    ta.seed = in.seed;
+    ta.run = in.run;
+    ta.step = in.step;
+    ta.step_dev = in.step_dev;
+    ta.key_shift = 53 - std::max(1, ceil_log2_u64((uint64_t)std::max<int64_t>(p->n_items, 2)));
+    ta.cell_h = p->cell_h;
+    ta.cell_bucket_base = p->cell_bucket_base;
+    ta.B = p->B;
+    ta.seg_off = p->seg_off;
+    ta.seg_run = p->seg_run;
+    ta.big_cells = p->big_cells;
+    ta.n_big = p->n_big;
+    ta.tile_off = p->tile_off;
+    ta.rec_key = p->rec_key;
+    ta.rec_s = p->rec_s;
+    ta.rec_xi = p->rec_xi;
+    ta.rec_v = p->rec_v;
+    ta.cell_tot = p->cell_tot;
+    ta.n_acc = p->n_acc;
+    ta.err = ctx->err_dev;
+    const int ept = p->tile / TILE_THREADS;
+    const size_t lds = (size_t)(((p->B + 1) * 4 + 15) & ~15) + (size_t)p->tile * 8;
     mark(0);
-    hipLaunchKernelGGL((k_scatter<SCATTER_THREADS, SCATTER_EPT>), dim3(grid1),
-                       dim3(SCATTER_THREADS), (size_t)p->lds_bins * 4, stream, sa);
+    if (list) {
+        if (ept == 16)
+            launch_tile<16, true>(p->n_tiles, lds, stream, ta);
+        else if (ept == 8)
+            launch_tile<8, true>(p->n_tiles, lds, stream, ta);
+        else
+            launch_tile<4, true>(p->n_tiles, lds, stream, ta);
+    } else {
+        if (ept == 16)
+            launch_tile<16, false>(p->n_tiles, lds, stream, ta);
+        else if (ept == 8)
+            launch_tile<8, false>(p->n_tiles, lds, stream, ta);
+        else
+            launch_tile<4, false>(p->n_tiles, lds, stream, ta);
+    }
     SDM_HIP(hipGetLastError());
 
     GroupArgs ga{};
     ga.mode = p->mode;
+    ga.B = p->B;
+    ga.n_tiles = p->n_tiles;
+    ga.tile = p->tile;
+    ga.n_cell = p->n_cell;
     ga.group_first = p->group_first;
     ga.bucket_cell = p->bucket_cell;
-    ga.slot_base = p->slot_base;
     ga.sub_bits = p->sub_bits;
     ga.cell_h = p->cell_h;
-    ga.cursor = p->cursor;
-    ga.rank_off = p->rank_off;
-    ga.cell_start = cell_start;
+    ga.cell_bucket_base = p->cell_bucket_base;
+    ga.cell_big = p->cell_big;
+    ga.tile_off = p->tile_off;
     ga.rec_key = p->rec_key;
     ga.rec_s = p->rec_s;
     ga.rec_xi = p->rec_xi;
     ga.rec_v = p->rec_v;
-    ga.ov_count = p->ov_count;
-    ga.ov_key = p->ov_key;
-    ga.ov_s = p->ov_s;
-    ga.ov_bucket = p->ov_bucket;
+    ga.cell_id = in.cell_id;
+    ga.cell_tot = p->cell_tot;
+    ga.n_acc = p->n_acc;
+    ga.gstat = p->gstat;
+    ga.cstat = p->cstat;
+    ga.cell_start = cell_start;
     ga.sk = p->sk;
     ga.ss = p->ss;
     ga.sb = p->sb;
@@ -1127,44 +1358,47 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
                        stream, ga);
     SDM_HIP(hipGetLastError());
 
-    SeamArgs ta{};
-    ta.mode = p->mode;
-    ta.G = p->G;
-    ta.seam_open = p->seam_open;
-    ta.seam_close = p->seam_close;
-    ta.seam_state = p->seam_state;
-    ta.group_tot = p->group_tot;
-    ta.cell_start = cell_start;
-    ta.xi = in.xi;
-    ta.attr = in.attr;
-    ta.n_attr = in.n_attr;
-    ta.stride = in.stride;
-    ta.dt = in.dt;
-    ta.dv_cell = in.dv_cell;
-    ta.dv = in.dv;
-    ta.kern = in.kern;
-    ta.seg_off = p->seg_off;
-    ta.seg_run = p->seg_run;
-    ta.seg_kernel = p->seg_kernel;
-    ta.seg_dv = p->seg_dv;
-    ta.kernels = p->kernels;
-    ta.seed = in.seed;
-    ta.run = in.run;
-    ta.step = in.step;
-    ta.step_dev = in.step_dev;
-    ta.slot_cell_local = in.slot_cell_local ? 1 : 0;
-    ta.counters = in.counters;
-    ta.gamma_out = in.gamma_out;
-    ta.ov_count = p->ov_count;
-    ta.ticket = p->ticket + 1;
-    ta.step_advance = in.step_advance;
-    constexpr int ST = 256;
-    const int grid3 = std::max(1, (p->G + ST - 1) / ST);
+    FinishArgs fa{};
+    fa.mode = p->mode;
+    fa.G = p->G;
+    fa.n_cell = p->n_cell;
+    fa.seam_open = p->seam_open;
+    fa.seam_close = p->seam_close;
+    fa.seam_state = p->seam_state;
+    fa.group_tot = p->group_tot;
+    fa.xi = in.xi;
+    fa.attr = in.attr;
+    fa.n_attr = in.n_attr;
+    fa.stride = in.stride;
+    fa.dt = in.dt;
+    fa.dv_cell = in.dv_cell;
+    fa.dv = in.dv;
+    fa.kern = in.kern;
+    fa.seg_off = p->seg_off;
+    fa.seg_run = p->seg_run;
+    fa.seg_kernel = p->seg_kernel;
+    fa.seg_dv = p->seg_dv;
+    fa.kernels = p->kernels;
+    fa.seed = in.seed;
+    fa.run = in.run;
+    fa.step = in.step;
+    fa.step_dev = in.step_dev;
+    fa.slot_cell_local = in.slot_cell_local ? 1 : 0;
+    fa.counters = in.counters;
+    fa.gamma_out = in.gamma_out;
+    fa.big_cells = p->big_cells;
+    fa.n_big = p->n_big;
+    fa.cell_tot = p->cell_tot;
+    fa.n_acc = p->n_acc;
+    fa.cell_start = cell_start;
+    fa.n_live_out = n_live_out;
+    fa.step_advance = in.step_advance;
+    constexpr int FT = 256;
+    const int grid3 = std::max(1, (p->G + FT - 1) / FT);
     mark(2);
-    hipLaunchKernelGGL((k_seams<ST>), dim3(grid3), dim3(ST), 0, stream, ta);
+    hipLaunchKernelGGL((k_finish<FT>), dim3(grid3), dim3(FT), 0, stream, fa);
     SDM_HIP(hipGetLastError());
     mark(3);
-    (void)fused;
 }
 
 }  // namespace sdm

@@ -34,33 +34,41 @@ struct HipError {
 // ------------------------------------------------------------ engine plan
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
-// Records carried through the sort: one slot per SD.
+// Pair that straddles two groups: the opener's record, written by the
+// group holding it and completed by the seam kernel.
 struct SeamRec {
     uint64_t xi;
     double v;
     uint32_t s;
     uint32_t rank;
     int32_t cell;
+    uint32_t cs;   // rank of the cell's first SD
+    uint32_t n_c;  // live SDs in the cell
     uint32_t pad;
 };
 
 // Bucketed sort plan.  The live SDs of cell c are split by the top h[c]
-// bits of their 53-bit shuffle key into 2^h[c] buckets; each bucket owns a
-// fixed region of cap slots in the record arrays (records beyond the
-// capacity go to an overflow list).  Groups of consecutive buckets are
-// sorted by one workgroup each.
+// bits of their 53-bit shuffle key into 2^h[c] buckets.  The scatter
+// kernel sorts each tile of T SD slots by bucket in LDS and writes the
+// tile's records contiguously, with its per-bucket offsets; a group of
+// consecutive buckets is then gathered from every tile and sorted by one
+// workgroup.  Cells whose buckets span several groups ("big" cells) get
+// their live count from per-tile atomics and their start rank from the
+// group holding their first bucket.
 struct Plan {
     int mode = 0;
     int64_t n_items = 0;  // SD slots (fused) or index capacity (list modes)
     int32_t n_cell = 0;
     int32_t B = 0, G = 0;
-    int32_t lds_bins = 0;
-    uint32_t S = 0;  // total record slots
+    int32_t tile = 0;     // SD slots per scatter tile
+    int32_t n_tiles = 0;
+    int32_t n_big = 0;
     // device tables
     int32_t *cell_h = nullptr;            // [C]
     int32_t *cell_bucket_base = nullptr;  // [C+1]
+    uint8_t *cell_big = nullptr;          // [C]
+    int32_t *big_cells = nullptr;         // [n_big]
     int32_t *bucket_cell = nullptr;       // [B]
-    uint32_t *slot_base = nullptr;        // [B+1]
     uint8_t *sub_bits = nullptr;          // [B]
     int32_t *group_first = nullptr;       // [G+1]
     // per-cell run description (batched plans); null for single-run plans
@@ -70,29 +78,25 @@ struct Plan {
     double *seg_dv = nullptr;             // [C]
     KernelDesc *kernels = nullptr;        // [n_kernels]
     // workspace
-    uint32_t *cursor = nullptr;           // [B] (zero between launches)
-    uint32_t *rank_off = nullptr;         // [B+1]
-    uint32_t *cell_start_ws = nullptr;    // [C+1] (batched plans)
+    uint16_t *tile_off = nullptr;         // [n_tiles][B+1]
+    uint64_t *rec_key = nullptr;          // [n_tiles * tile]
+    uint32_t *rec_s = nullptr;
+    uint64_t *rec_xi = nullptr;           // (fused)
+    double *rec_v = nullptr;              // (fused)
+    uint32_t *cell_tot = nullptr;         // [C] (big cells; zero between launches)
+    uint32_t *n_acc = nullptr;            // [0] live total [1] group ticket [2] epoch [3] seam ticket
+    uint64_t *gstat = nullptr;            // [G] look-back status
+    uint64_t *cstat = nullptr;            // [C] start rank of big cells
+    uint32_t *cell_start_ws = nullptr;    // [C+1]
     int64_t *n_live_ws = nullptr;         // [1]
-    uint32_t *ticket = nullptr;           // [1]
-    uint64_t *rec_key = nullptr;          // [S]
-    uint32_t *rec_s = nullptr;            // [S]
-    uint64_t *rec_xi = nullptr;           // [S] (fused)
-    double *rec_v = nullptr;              // [S] (fused)
-    uint32_t *ov_count = nullptr;         // [1]
-    uint64_t *ov_key = nullptr;           // [n_items]
-    uint32_t *ov_s = nullptr;             // [n_items]
-    uint32_t *ov_bucket = nullptr;        // [n_items]
-    uint64_t *sk = nullptr;               // [2 n_items] slow-path scratch
-    uint32_t *ss = nullptr;               // [2 n_items]
-    uint32_t *sb = nullptr;               // [2 n_items]
+    uint64_t *sk = nullptr;               // [2 n_items + 8] global-sort scratch
+    uint32_t *ss = nullptr;
+    uint32_t *sb = nullptr;
     SeamRec *seam_open = nullptr;         // [G]
     SeamRec *seam_close = nullptr;        // [G]
     uint32_t *seam_state = nullptr;       // [G]
     uint32_t *group_tot = nullptr;        // [G]
     std::vector<void *> allocs;
-    int group_threads = 512;
-    int group_ept = 6;
 };
 
 struct PlanKey {
@@ -118,7 +122,7 @@ struct sdm_ctx {
     uint32_t *tmp_u32 = nullptr;       // [n_sd_max + 64] compaction scratch
     uint32_t *tile_cnt = nullptr;      // [tiles + 1]
     std::map<sdm::PlanKey, sdm::Plan *> plans;
-    int32_t dbg_bucket_cap = 0;        // testing: force tiny bucket regions
+    int32_t dbg_bucket_target = 0;     // testing: expected SDs per bucket
     int32_t dbg_group_cap = -1;        // testing: force the global-memory sort
 };
 
