@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the SDM step of one run on one "
@@ -155,6 +157,15 @@ def main():
     print("bench: n_sd=2^%d warmup=%d steps=%d" % (args.log2_n_sd, args.warmup, args.steps),
           file=sys.stderr, flush=True)
 
+    if args.calib_copy:
+        # A copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
+        # the counters of the SDM kernels to bytes.
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         ctx.step(st, w["dt"], k, r, **kw)
     torch.cuda.synchronize()

@@ -37,15 +37,15 @@
 namespace sdm {
 
 constexpr int TILE_THREADS = 1024;
-constexpr int GROUP_THREADS = 512;
+constexpr int GROUP_THREADS = 1024;
 constexpr int GROUP_EPT = 6;
-constexpr int MAXB = 256;            // buckets per group
+constexpr int MAXB = 64;             // buckets per group
 constexpr int NSUB = 1024;           // sub-buckets per group
 constexpr int MAX_TILES = 1024;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
-constexpr double BUCKET_TARGET = 2048.0;
-constexpr double GROUP_TARGET = 2048.0;
+constexpr double BUCKET_TARGET = 4096.0;
+constexpr double GROUP_TARGET = 4096.0;
 constexpr uint32_t NO_BUCKET = 0xFFFFu;
 
 // look-back status word: kind (2 bits) | epoch (30 bits) | value (32 bits)
@@ -492,9 +492,11 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
 }
 
 // ------------------------------------------------------- pair evaluation
+// Per-cell constants of eq. (3) and of the gamma draw.
 struct PairCtx {
     double norm;         // (dt / dV_c) * F(n_c)
-    KernelDesc kd;
+    int32_t kid;         // kernel id
+    double kp;           // kernel parameter p[0]
     uint32_t run;
     uint32_t slot_base;  // rank from which slots are numbered
     uint32_t gbase;      // offset of the run's slots in gamma_out
@@ -507,12 +509,15 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
     double dvc;
     if (a.seg_run) {
         dvc = a.seg_dv[c];
-        pc.kd = a.kernels[a.seg_kernel[c]];
+        const int ki = a.seg_kernel[c];
+        pc.kid = a.kernels[ki].id;
+        pc.kp = a.kernels[ki].p[0];
         pc.run = (uint32_t)a.seg_run[c];
         pc.gbase = a.seg_off[c] >> 1;
     } else {
         dvc = a.dv_cell ? a.dv_cell[c] : a.dv;
-        pc.kd = a.kern;
+        pc.kid = a.kern.id;
+        pc.kp = a.kern.p[0];
         pc.run = a.run;
         pc.gbase = 0;
     }
@@ -525,7 +530,12 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
 __device__ __forceinline__ double pair_prob(const PairCtx &pc, uint64_t xa, double va,
                                             uint64_t xb, double vb)
 {
-    const double ak = kernel_value(pc.kd, va, vb);
+    KernelDesc kd;
+    kd.id = pc.kid;
+    kd.reserved = 0;
+    kd.p[0] = pc.kp;
+    kd.p[1] = kd.p[2] = kd.p[3] = 0.0;
+    const double ak = kernel_value(kd, va, vb);
     const uint64_t xm = xa > xb ? xa : xb;
     return (ak * (double)xm) * pc.norm;
 }
@@ -543,12 +553,19 @@ __device__ __forceinline__ void finish_pair(const Args &a, const PairCtx &pc, ui
         apply_collision(col, sa, sbb, a.xi, a.attr, a.n_attr, a.stride);
 }
 
+// Per-local-bucket tables of a group, in LDS.
+struct GroupTabs {
+    uint32_t *off;     // [nb+1] local offset of each bucket
+    uint32_t *cs;      // [nb] rank of the first SD of the bucket's cell
+    uint32_t *n;       // [nb] live SDs in the bucket's cell
+    PairCtx *pc;       // [nb] per-cell constants (fused mode)
+};
+
 // Output phase shared by the LDS and the global-memory paths.  Get gives
-// s / xi / v at local position f; t_* are the per-local-bucket tables.
+// s / xi / v at local position f.
 template <int THREADS, class Get>
 __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_t tot,
-                              uint32_t rank0, const uint32_t *t_off, const uint32_t *t_cs,
-                              const uint32_t *t_n, const Get &get, uint32_t *red,
+                              uint32_t rank0, const GroupTabs &T, const Get &get, uint32_t *red,
                               uint32_t *s_misc, uint32_t *opl)
 {
     const int tid = threadIdx.x;
@@ -563,10 +580,12 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
     const uint32_t f0 = min(tot, tid * per), f1 = min(tot, f0 + per);
     uint32_t cnt = 0;
     uint32_t state = 0;
+    int bl = f0 < f1 ? upper_index(T.off, nb, f0) : 0;
     for (uint32_t f = f0; f < f1; ++f) {
-        const int bl = upper_index(t_off, nb, f);
+        while (f >= T.off[bl + 1])
+            ++bl;
         const uint32_t r = rank0 + f;
-        const uint32_t cs = t_cs[bl], ce = cs + t_n[bl];
+        const uint32_t cs = T.cs[bl], ce = cs + T.n[bl];
         const uint32_t ic = r - cs;
         const bool opener = ((ic & 1u) == 0u) && (r + 1 < ce);
         if (opener && f + 1 < tot) {
@@ -579,7 +598,7 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             rec.rank = r;
             rec.cell = a.bucket_cell[b0 + bl];
             rec.cs = cs;
-            rec.n_c = t_n[bl];
+            rec.n_c = T.n[bl];
             rec.pad = 0;
             if (opener) {
                 a.seam_open[g] = rec;
@@ -594,29 +613,30 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
         atomicOr(&s_misc[2], state);
     uint32_t n_op;
     uint32_t w = block_exclusive_scan<THREADS>(cnt, red, &n_op);
+    bl = f0 < f1 ? upper_index(T.off, nb, f0) : 0;
     for (uint32_t f = f0; f < f1 && cnt; ++f) {
-        const int bl = upper_index(t_off, nb, f);
+        while (f >= T.off[bl + 1])
+            ++bl;
         const uint32_t r = rank0 + f;
-        const uint32_t cs = t_cs[bl], ce = cs + t_n[bl];
+        const uint32_t cs = T.cs[bl], ce = cs + T.n[bl];
         const uint32_t ic = r - cs;
         if (((ic & 1u) == 0u) && (r + 1 < ce) && f + 1 < tot)
-            opl[w++] = f;
+            opl[w++] = f | ((uint32_t)bl << 16);
     }
     __syncthreads();
     // 2. pairs, two consecutive openers per thread so that slots 2u, 2u+1
     //    share one Philox block when they are adjacent
     uint32_t shift = 0;
     if (n_op) {
-        const uint32_t fa = opl[0];
-        const int bl = upper_index(t_off, nb, fa);
-        const uint32_t base = a.slot_cell_local ? t_cs[bl] : 0u;
-        shift = ((rank0 + fa - base) >> 1) & 1u;
+        const uint32_t e0 = opl[0];
+        const uint32_t fa = e0 & 0xFFFFu, b = e0 >> 16;
+        shift = ((rank0 + fa - T.pc[b].slot_base) >> 1) & 1u;
     }
     for (uint32_t j = tid; 2 * j < n_op + shift; j += THREADS) {
         const int k0 = (int)(2 * j) - (int)shift;
         uint32_t qv[2] = {0, 0};
         double pv[2] = {0.0, 0.0};
-        PairCtx pcv[2];
+        uint32_t runv[2] = {0, 0}, bv[2] = {0, 0};
         uint32_t sa[2] = {0, 0}, sb_[2] = {0, 0};
         uint64_t xa[2] = {0, 0}, xb[2] = {0, 0};
         bool valid[2];
@@ -626,24 +646,24 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             valid[u] = k >= 0 && k < (int)n_op;
             if (!valid[u])
                 continue;
-            const uint32_t f = opl[k];
-            const int bl = upper_index(t_off, nb, f);
-            const int32_t c = a.bucket_cell[b0 + bl];
-            pcv[u] = pair_ctx(a, c, t_cs[bl], t_n[bl]);
-            const uint32_t r = rank0 + f;
-            qv[u] = (r - pcv[u].slot_base) >> 1;
+            const uint32_t e = opl[k];
+            const uint32_t f = e & 0xFFFFu;
+            bv[u] = e >> 16;
+            const PairCtx &pc = T.pc[bv[u]];
+            runv[u] = pc.run;
+            qv[u] = (rank0 + f - pc.slot_base) >> 1;
             sa[u] = get.s(f);
             xa[u] = get.xi(f);
             const double va = get.v(f);
             sb_[u] = get.s(f + 1);
             xb[u] = get.xi(f + 1);
             const double vb = get.v(f + 1);
-            pv[u] = pair_prob(pcv[u], xa[u], va, xb[u], vb);
+            pv[u] = pair_prob(pc, xa[u], va, xb[u], vb);
         }
         double phi[2] = {0.0, 0.0};
         if (valid[0] && valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1 &&
-            pcv[0].run == pcv[1].run) {
-            const WordPair wp = philox_words(a.seed, pcv[0].run, step, SDM_STREAM_GAMMA,
+            runv[0] == runv[1]) {
+            const WordPair wp = philox_words(a.seed, runv[0], step, SDM_STREAM_GAMMA,
                                              qv[0] >> 1);
             phi[0] = word_to_uniform(wp.even);
             phi[1] = word_to_uniform(wp.odd);
@@ -652,14 +672,16 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             for (int u = 0; u < 2; ++u)
                 if (valid[u])
                     phi[u] = word_to_uniform(
-                        philox_word(a.seed, pcv[u].run, step, SDM_STREAM_GAMMA, qv[u]));
+                        philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u]));
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u)
             if (valid[u])
-                finish_pair(a, pcv[u], qv[u], pv[u], phi[u], sa[u], xa[u], sb_[u], xb[u], st);
+                finish_pair(a, T.pc[bv[u]], qv[u], pv[u], phi[u], sa[u], xa[u], sb_[u], xb[u],
+                            st);
     }
-    flush_stats<THREADS>(st, a.counters, red);
+    if (a.counters)
+        flush_stats<THREADS>(st, a.counters, red);
     if (tid == 0) {
         a.seam_state[g] = s_misc[2];
         a.group_tot[g] = tot;
@@ -710,6 +732,59 @@ __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int
     return b - (uint32_t)b0;
 }
 
+// Block-wide decoupled look-back: exclusive prefix of the group totals of
+// groups [0, g), THREADS predecessors per round (one per thread).  The
+// nearest inclusive prefix in the window ends the walk once every group
+// after it in the window has published its aggregate.
+template <int THREADS>
+__device__ uint32_t look_back(const GroupArgs &a, int g, uint32_t epoch, uint32_t *lb,
+                              uint32_t *red)
+{
+    const int tid = threadIdx.x;
+    const uint32_t ep = epoch & 0x3FFFFFFFu;
+    uint64_t prefix = 0;
+    int j0 = g - 1;
+    while (g > 0) {
+        const int j = j0 - tid;
+        const uint64_t w = j >= 0 ? load64_agent(&a.gstat[j]) : st_pack(ST_PRE, epoch, 0);
+        const uint64_t kind = w >> 62;
+        const bool ready = kind != 0 && (((uint32_t)(w >> 32) & 0x3FFFFFFFu) == ep);
+        if (tid == 0) {
+            lb[0] = THREADS;  // nearest inclusive prefix
+            lb[1] = 0;        // someone before it is not ready
+        }
+        __syncthreads();
+        if (ready && kind == ST_PRE)
+            atomicMin(&lb[0], (uint32_t)tid);
+        __syncthreads();
+        const uint32_t p = lb[0];
+        if (!ready && (uint32_t)tid <= p)
+            lb[1] = 1;
+        __syncthreads();
+        const bool retry = lb[1] != 0;
+        if (!retry) {
+            uint64_t v = ((uint32_t)tid <= p && ready) ? (uint64_t)(uint32_t)w : 0ull;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                v += __shfl_xor(v, o, 64);
+            if ((tid & 63) == 0) {
+                red[2 * (tid >> 6)] = (uint32_t)v;
+                red[2 * (tid >> 6) + 1] = (uint32_t)(v >> 32);
+            }
+        }
+        __syncthreads();
+        if (retry)
+            continue;
+        for (int wv = 0; wv < THREADS / 64; ++wv)
+            prefix += (uint64_t)red[2 * wv] | ((uint64_t)red[2 * wv + 1] << 32);
+        __syncthreads();
+        if (p < (uint32_t)THREADS)
+            break;
+        j0 -= THREADS;
+    }
+    return (uint32_t)prefix;
+}
+
 // --------------------------------------------------------------- k_group
 template <int THREADS, int EPT>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
@@ -724,9 +799,10 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t t_mask[MAXB];
     __shared__ uint32_t t_cs[MAXB];
     __shared__ uint32_t t_n[MAXB];
+    __shared__ PairCtx t_pc[MAXB];
     // sub-bucket histogram during the sort, opener list afterwards
     __shared__ uint32_t sub_hist[(NSUB + 1) > (CAP / 2 + 1) ? (NSUB + 1) : (CAP / 2 + 1)];
-    __shared__ uint32_t red[5 * (THREADS / 64) + 8];
+    __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans, look-back and flush_stats
     __shared__ uint32_t s_misc[8];
     __shared__ __align__(16) unsigned char pool[CAP * 20];
 
@@ -743,8 +819,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     const int nb = b1 - b0;
     const int nt = a.n_tiles;
     const int64_t Bp = a.B + 1;
+    const bool fused = a.mode == MODE_FUSED;
 
-    // this group's run in every tile
+    // 1. this group's run in every tile; bucket tables; big-cell sizes
     for (int t = tid; t < nt; t += THREADS) {
         const uint32_t lo = a.tile_off[t * Bp + b0];
         const uint32_t hi = a.tile_off[t * Bp + b1];
@@ -753,43 +830,35 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     }
     for (int i = tid; i < nb; i += THREADS) {
         const int b = b0 + i;
-        const int h = a.cell_h[a.bucket_cell[b]];
+        const int c = a.bucket_cell[b];
+        const int h = a.cell_h[c];
         const int u = a.sub_bits[b];
         t_shift[i] = (uint32_t)(53 - h - u);
         t_mask[i] = (1u << u) - 1u;
         t_subbase[i] = 1u << u;
-        if (nb > 1) {
-            uint32_t c = 0;
-            for (int t = 0; t < nt; ++t)
-                c += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
-            t_cnt[i] = c;
-        }
+        t_n[i] = a.cell_big[c] ? load32_agent(&a.cell_tot[c]) : 0u;
+        t_cnt[i] = 0;
     }
     __syncthreads();
+    if (nb > 1) {
+        // per-bucket counts of this group, summed over the tiles
+        for (int idx = tid; idx < nb * nt; idx += THREADS) {
+            const int i = idx / nt, t = idx - i * nt;
+            const int b = b0 + i;
+            const uint32_t d =
+                (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
+            if (d)
+                atomicAdd(&t_cnt[i], d);
+        }
+        __syncthreads();
+    }
     lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, nt, red);
     const uint32_t tot = run_pre[nt];
     if (tid == 0) {
+        // publish this group's total at once: the sort below needs no rank
+        store64_agent(&a.gstat[g], st_pack(g == 0 ? ST_PRE : ST_AGG, epoch, tot));
         if (nb == 1)
             t_cnt[0] = tot;
-        // decoupled look-back over the groups for this group's first rank
-        store64_agent(&a.gstat[g], st_pack(g == 0 ? ST_PRE : ST_AGG, epoch, tot));
-        uint32_t prefix = 0;
-        if (g > 0) {
-            int j = g - 1;
-            while (true) {
-                const uint64_t w = load64_agent(&a.gstat[j]);
-                const uint32_t we = (uint32_t)(w >> 32) & 0x3FFFFFFFu;
-                const uint64_t kind = w >> 62;
-                if (kind == 0 || we != (epoch & 0x3FFFFFFFu))
-                    continue;
-                prefix += (uint32_t)w;
-                if (kind == ST_PRE)
-                    break;
-                --j;
-            }
-            store64_agent(&a.gstat[g], st_pack(ST_PRE, epoch, prefix + tot));
-        }
-        s_misc[3] = prefix;
         uint32_t off = 0, sub = 0;
         for (int i = 0; i < nb; ++i) {
             t_off[i] = off;
@@ -800,65 +869,32 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
         t_off[nb] = off;
         t_subbase[nb] = sub;
-        // start rank of a big cell that began in an earlier group
-        const int c0 = a.bucket_cell[b0];
-        if (a.cell_bucket_base[c0] < b0) {
-            uint64_t w;
-            do {
-                w = load64_agent(&a.cstat[c0]);
-            } while ((uint32_t)(w >> 32) != epoch + 1u);
-            s_misc[4] = (uint32_t)w;
-        }
     }
-    __syncthreads();
-    const uint32_t rank0 = s_misc[3];
-    // per-local-bucket cell start and cell size
-    for (int i = tid; i < nb; i += THREADS) {
-        const int b = b0 + i;
-        const int c = a.bucket_cell[b];
-        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
-        uint32_t cs;
-        if (first >= b0) {
-            cs = rank0 + t_off[first - b0];
-            if (b == first) {
-                a.cell_start[c] = cs;
-                if (a.cell_big[c])
-                    store64_agent(&a.cstat[c], ((uint64_t)(epoch + 1u) << 32) | cs);
-            }
-        } else {
-            cs = s_misc[4];
-        }
-        uint32_t n_c;
-        if (a.cell_big[c])
-            n_c = load32_agent(&a.cell_tot[c]);
-        else
-            n_c = t_off[last - b0] - t_off[first - b0];
-        t_cs[i] = cs;
-        t_n[i] = n_c;
-    }
-    __syncthreads();
     const uint32_t cap_here =
         a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
-    const bool fused = a.mode == MODE_FUSED;
+    const bool lds_path = tot <= cap_here;
+    for (uint32_t i = tid; i <= (uint32_t)NSUB; i += THREADS)
+        sub_hist[i] = 0;
+    __syncthreads();
 
-    if (tot <= cap_here) {
-        // ------------------------------------------------ LDS path
+    uint64_t *XF = reinterpret_cast<uint64_t *>(pool);
+    double *VF = reinterpret_cast<double *>(pool + 8 * CAP);
+    uint32_t *SF = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
+    if (lds_path) {
+        // 2. gather the records and sort them in LDS: counting sort by
+        //    (bucket, next key bits), then exact ranks by (key, s)
         uint64_t *K1 = reinterpret_cast<uint64_t *>(pool);
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
         uint16_t *O1 = reinterpret_cast<uint16_t *>(pool + 12 * CAP);
         uint16_t *SB1 = reinterpret_cast<uint16_t *>(pool + 14 * CAP);
         uint16_t *FP = reinterpret_cast<uint16_t *>(pool + 16 * CAP);
         const uint32_t nsub = t_subbase[nb];
-        for (uint32_t i = tid; i <= nsub; i += THREADS)
-            sub_hist[i] = 0;
-        __syncthreads();
         uint64_t key[EPT], xv[EPT];
         double vv[EPT];
         uint32_t sid[EPT], sbk[EPT], lrk[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
-            sbk[e] = 0xFFFFFFFFu;
             if (li < tot) {
                 const int t = upper_index(run_pre, nt, li);
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
@@ -871,6 +907,13 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                     xv[e] = 0;
                     vv[e] = 0.0;
                 }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const uint32_t li = (uint32_t)(e * THREADS + tid);
+            sbk[e] = 0xFFFFFFFFu;
+            if (li < tot) {
                 const uint32_t bl = local_bucket(a, b0, nb, key[e], sid[e]);
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
                 sbk[e] = t_subbase[bl] + sub;
@@ -913,9 +956,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             if (sbk[e] != 0xFFFFFFFFu)
                 fp[e] = FP[e * THREADS + tid];
         __syncthreads();
-        uint64_t *XF = reinterpret_cast<uint64_t *>(pool);
-        double *VF = reinterpret_cast<double *>(pool + 8 * CAP);
-        uint32_t *SF = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (sbk[e] != 0xFFFFFFFFu) {
@@ -924,11 +964,53 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 SF[fp[e]] = sid[e];
             }
         }
-        __syncthreads();
+    }
+
+    // 3. rank offset of the group (all predecessors have long published
+    //    their totals), cell starts, per-cell constants
+    const uint32_t rank0 = look_back<THREADS>(a, g, epoch, &s_misc[4], red);
+    if (tid == 0) {
+        if (g > 0)
+            store64_agent(&a.gstat[g], st_pack(ST_PRE, epoch, rank0 + tot));
+        const int c0 = a.bucket_cell[b0];
+        if (a.cell_bucket_base[c0] < b0) {
+            // start rank of a big cell that began in an earlier group
+            uint64_t w;
+            do {
+                w = load64_agent(&a.cstat[c0]);
+            } while ((uint32_t)(w >> 32) != epoch + 1u);
+            s_misc[3] = (uint32_t)w;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += THREADS) {
+        const int b = b0 + i;
+        const int c = a.bucket_cell[b];
+        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
+        uint32_t cs;
+        if (first >= b0) {
+            cs = rank0 + t_off[first - b0];
+            if (b == first) {
+                a.cell_start[c] = cs;
+                if (a.cell_big[c])
+                    store64_agent(&a.cstat[c], ((uint64_t)(epoch + 1u) << 32) | cs);
+            }
+        } else {
+            cs = s_misc[3];
+        }
+        const uint32_t n_c = a.cell_big[c] ? t_n[i] : t_off[last - b0] - t_off[first - b0];
+        t_cs[i] = cs;
+        t_n[i] = n_c;
+        if (fused)
+            t_pc[i] = pair_ctx(a, c, cs, n_c);
+    }
+    __syncthreads();
+    const GroupTabs T{t_off, t_cs, t_n, t_pc};
+
+    if (lds_path) {
         LdsGet get{SF, XF, VF};
         // the opener list reuses the sub-bucket histogram (dead after ranking)
-        group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, t_cs, t_n, get, red, s_misc,
-                               sub_hist);
+        group_outputs<THREADS>(a, g, b0, nb, tot, rank0, T, get, red, s_misc, sub_hist);
         return;
     }
 
@@ -937,8 +1019,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     // P = next power of two >= tot (ranges of consecutive groups are disjoint
     // since P <= 2 tot), and sorted there by (bucket, key, s) with a bitonic
     // network.  The pair phase then reads xi and v from the state; its
-    // opener list lives in scratch too (at 2 rank0 + P .. in the ss array of
-    // the next half), so any group size is handled.
+    // opener list reuses the group's bucket scratch.
     const uint32_t base2 = 2u * rank0;
     uint32_t P = 1;
     while (P < tot)
@@ -984,9 +1065,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
     }
     GlobalGet get{a.ss + base2, fused ? a.xi : nullptr, fused ? a.attr : nullptr};
-    // opener list in the (now free) bucket scratch of this group
-    group_outputs<THREADS>(a, g, b0, nb, tot, rank0, t_off, t_cs, t_n, get, red, s_misc,
-                           a.sb + base2);
+    group_outputs<THREADS>(a, g, b0, nb, tot, rank0, T, get, red, s_misc, a.sb + base2);
 }
 
 // -------------------------------------------------------------- k_finish
@@ -1013,7 +1092,7 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
             finish_pair(a, pc, q, p, phi, op.s, op.xi, cl.s, cl.xi, st);
         }
     }
-    if (a.mode == MODE_FUSED)
+    if (a.mode == MODE_FUSED && a.counters)
         flush_stats<THREADS>(st, a.counters, red);
     if (blockIdx.x == 0) {
         for (int i = threadIdx.x; i < a.n_big; i += THREADS)
