@@ -100,3 +100,42 @@ def ensemble(seed: int = 4, n_runs: int = 1024, log2_min: float = 8.0,
         runs.append(dict(n_sd=n, xi=xi, attr=v[None, :].copy(), kernel_id=kid,
                          kparams=kp, dv=BOX_DV, run=r))
     return dict(n_runs=n_runs, sizes=sizes, runs=runs, dt=dt)
+
+
+def ensemble_layout(ens):
+    """Concatenates the members of an ensemble into one batch state: member r
+    occupies SD slots [offset_r, offset_r + n_r) with even offsets (one
+    padding slot of multiplicity 0 after odd-sized members).  Returns
+    (xi, attr[1, N], segments) with segments = (offset, n, dv, kernel_id,
+    kparams, run)."""
+    offs, off = [], 0
+    for m in ens["runs"]:
+        offs.append(off)
+        off += m["n_sd"] + (m["n_sd"] & 1)
+    n_tot = off
+    xi = np.zeros(n_tot, np.uint64)
+    v = np.zeros(n_tot, np.float64)
+    segs = []
+    for m, o in zip(ens["runs"], offs):
+        n = m["n_sd"]
+        xi[o:o + n] = m["xi"]
+        v[o:o + n] = m["attr"][0]
+        segs.append((o, n, m["dv"], m["kernel_id"], m["kparams"], m["run"]))
+    return xi, v[None, :], segs
+
+
+
+MLP_LAYERS = (5, 128, 128, 128, 3)
+
+
+def mlp_init(seed: int = 7):
+    """Initial parameters of the surrogate network as one flat float32
+    vector (W1, b1, ..., W4, b4; W row-major [out][in]): every entry of a
+    layer with fan-in f uniform in [-1/sqrt(f), 1/sqrt(f)]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fi, fo in zip(MLP_LAYERS[:-1], MLP_LAYERS[1:]):
+        bound = 1.0 / math.sqrt(fi)
+        parts.append(rng.uniform(-bound, bound, fo * fi))
+        parts.append(rng.uniform(-bound, bound, fo))
+    return np.concatenate(parts).astype(np.float32)
