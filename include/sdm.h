@@ -260,6 +260,53 @@ int sdm_prepare_step(sdm_ctx *ctx, const sdm_state *st,
 int sdm_step(sdm_ctx *ctx, const sdm_state *st, const sdm_step_params *p,
              hipStream_t stream);
 
+/* --------------------------------------------------- batched ensemble */
+/* One independent run of a batch: SD slots [offset, offset + n_sd) of the
+ * batch state form one well-mixed cell (its own volume dv and kernel); the
+ * run's random streams use Philox run word `run` and run-local SD ids and
+ * pair slots, so every member gives exactly the result it gives alone. */
+typedef struct {
+    int64_t    offset;       /* first SD slot (even)                        */
+    int64_t    n_sd;         /* SD slots of the run                         */
+    double     dv;           /* [m^3]                                       */
+    sdm_kernel kernel;
+    uint32_t   run;          /* Philox run word                             */
+    uint32_t   reserved;
+} sdm_segment;
+
+/* Creates a batch of n_seg runs (blocking; the batch owns its plan and
+ * schedule tables until sdm_batch_destroy).  Segments must be sorted by
+ * offset, non-overlapping, with even offsets; n_seg <= n_cell_max. */
+int sdm_batch_create(sdm_ctx *ctx, sdm_batch **b, const sdm_segment *segs,
+                     int32_t n_seg);
+int sdm_batch_destroy(sdm_ctx *ctx, sdm_batch *b);
+
+/* One timestep of every run of the batch in one three-kernel launch
+ * sequence (graph-capturable after the first call).  st->n_cell must equal
+ * the number of segments and st->cell_id is ignored; cell_start[r] receives
+ * the first rank of run r, idx the sorted live SDs of every run (global SD
+ * ids, run after run), gamma_out (optional) slot q of run r at
+ * offset_r/2 + q.  p->dt and p->rng.seed/step/step_dev apply to all runs;
+ * p->kernel, p->dv and p->rng.run are taken from the segments. */
+int sdm_batch_step(sdm_ctx *ctx, sdm_batch *b, const sdm_state *st,
+                   const sdm_step_params *p, hipStream_t stream);
+
+/* Sets the batch's schedule to candidate `schedule` (0 <= schedule <
+ * *n_schedules), or only reports the number of candidates when schedule < 0.
+ * Blocking. */
+int sdm_batch_set_schedule(sdm_ctx *ctx, sdm_batch *b, int32_t schedule,
+                           int32_t *n_schedules);
+
+/* Chooses the batch's block and segment schedule (key-bucket size and
+ * group packing) by timing `steps` steps of each candidate on the scratch
+ * state (which is advanced), or loads the choice from cache_path (a text
+ * file keyed by the segment-size layout; NULL = no cache) and stores it
+ * there.  Results never depend on the schedule.  Blocking.  *chosen (may
+ * be NULL) receives the index of the chosen candidate. */
+int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch,
+                 const sdm_step_params *p, int32_t steps, const char *cache_path,
+                 int32_t *chosen);
+
 /* --------------------------------------------------- moments */
 /* M[c][k] = sum over live s in cell c of xi_s v_s^k / dV_c, k = 0, 1, 2.
  * Needs idx sorted by cell with cell_start (as after a step).  M: device

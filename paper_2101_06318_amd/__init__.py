@@ -53,6 +53,11 @@ class StepParamsC(C.Structure):
                 ("expected_per_cell", C.c_double), ("events", C.c_void_p * 4)]
 
 
+class Segment(C.Structure):
+    _fields_ = [("offset", C.c_int64), ("n_sd", C.c_int64), ("dv", C.c_double),
+                ("kernel", Kernel), ("run", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _I32 = C.c_int32
@@ -81,6 +86,12 @@ SIGNATURES = {
     "sdm_update_attributes": (_INT, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P, _P, _P]),
     "sdm_prepare_step": (_INT, [_P, C.POINTER(StateC), C.POINTER(StepParamsC)]),
     "sdm_step": (_INT, [_P, C.POINTER(StateC), C.POINTER(StepParamsC), _P]),
+    "sdm_batch_create": (_INT, [_P, C.POINTER(_P), C.POINTER(Segment), _I32]),
+    "sdm_batch_destroy": (_INT, [_P, _P]),
+    "sdm_batch_step": (_INT, [_P, _P, C.POINTER(StateC), C.POINTER(StepParamsC), _P]),
+    "sdm_batch_set_schedule": (_INT, [_P, _P, _I32, C.POINTER(_I32)]),
+    "sdm_autotune": (_INT, [_P, _P, C.POINTER(StateC), C.POINTER(StepParamsC), _I32,
+                            C.c_char_p, C.POINTER(_I32)]),
     "sdm_moments": (_INT, [_P, _P, _P, _P, _P, _P, _I32, _P, _D, _P]),
     "sdm_reassign": (_INT, [_P, _P, _I64, _I32, C.POINTER(Rng), _P]),
 }
@@ -114,6 +125,12 @@ def _ptr(t):
     if t is None:
         return None
     return t.data_ptr()
+
+
+def _row_stride(a):
+    """Element stride between attribute rows (a single row: its length; the
+    stride of a size-1 dimension is arbitrary)."""
+    return int(a.shape[1]) if a.shape[0] == 1 else int(a.stride(0))
 
 
 def _stream(stream=None):
@@ -224,7 +241,7 @@ class Context:
 
     def update_attributes(self, xi, attr, gamma, pair_flag, idx, n_live, counters=None,
                           stream=None):
-        n_attr, stride = (attr.shape[0], attr.stride(0)) if attr.dim() == 2 else (1, attr.numel())
+        n_attr, stride = (attr.shape[0], _row_stride(attr)) if attr.dim() == 2 else (1, attr.numel())
         _check(lib().sdm_update_attributes(self._h, _ptr(xi), _ptr(attr), int(n_attr),
                                            int(stride), _ptr(gamma), _ptr(pair_flag), _ptr(idx),
                                            _ptr(n_live), _ptr(counters), _stream(stream)))
@@ -245,7 +262,7 @@ class Context:
         s.n_sd = st.n_sd
         s.n_cell = st.n_cell
         s.n_attr = st.attr.shape[0]
-        s.attr_stride = st.attr.stride(0)
+        s.attr_stride = _row_stride(st.attr)
         s.xi = _ptr(st.xi)
         s.attr = _ptr(st.attr)
         s.cell_id = _ptr(st.cell_id)
@@ -281,6 +298,57 @@ class Context:
         s = self._state(st)
         p = self._params(st, dt, k, r, **kw)
         _check(lib().sdm_step(self._h, C.byref(s), C.byref(p), _stream(stream)))
+
+
+class Batch:
+    """A batch of independent runs advanced together (sdm_batch_*).
+
+    segments: list of (offset, n_sd, dv, kernel_id, kparams, run)."""
+
+    def __init__(self, ctx, segments):
+        self.ctx = ctx
+        arr = (Segment * len(segments))()
+        for i, (off, n, dv, kid, kp, run) in enumerate(segments):
+            arr[i].offset, arr[i].n_sd, arr[i].dv = int(off), int(n), float(dv)
+            arr[i].kernel = kernel(kid, kp)
+            arr[i].run = int(run)
+        self.n_seg = len(segments)
+        self._h = C.c_void_p()
+        _check(lib().sdm_batch_create(ctx.handle, C.byref(self._h), arr, self.n_seg))
+
+    def close(self):
+        if self._h:
+            lib().sdm_batch_destroy(self.ctx.handle, self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, st, dt, r, stream=None, **kw):
+        s = self.ctx._state(st)
+        p = Context._params(st, dt, kernel(0), r, dv=1.0, **kw)
+        _check(lib().sdm_batch_step(self.ctx.handle, self._h, C.byref(s), C.byref(p),
+                                    _stream(stream)))
+
+    def set_schedule(self, schedule):
+        n = C.c_int32(0)
+        _check(lib().sdm_batch_set_schedule(self.ctx.handle, self._h, int(schedule), C.byref(n)))
+        return int(n.value)
+
+    def n_schedules(self):
+        return self.set_schedule(-1)
+
+    def autotune(self, scratch, dt, r, steps=3, cache_path=None):
+        s = self.ctx._state(scratch)
+        p = Context._params(scratch, dt, kernel(0), r, dv=1.0)
+        chosen = C.c_int32(-1)
+        _check(lib().sdm_autotune(self.ctx.handle, self._h, C.byref(s), C.byref(p), int(steps),
+                                  cache_path.encode() if cache_path else None,
+                                  C.byref(chosen)))
+        return int(chosen.value)
 
 
 class State:

@@ -5,7 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
+#include <string>
 
 #include "sdm_internal.h"
 
@@ -43,29 +47,6 @@ __global__ void k_fill_zero_f64(double *p, int64_t n)
         p[i] = 0.0;
 }
 
-#define SDM_TRY try {
-#define SDM_CATCH                                                                     \
-    }                                                                                 \
-    catch (const ::sdm::HipError &he)                                                 \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_HIP, "%s: %s", he.what, hipGetErrorString(he.e));    \
-    }                                                                                 \
-    catch (const std::bad_alloc &)                                                    \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_NOMEM, "host allocation failed");                    \
-    }                                                                                 \
-    catch (...)                                                                       \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_STATE, "unexpected exception");                      \
-    }                                                                                 \
-    return SDM_OK;
-
-#define REQUIRE(cond, ...)                                  \
-    do {                                                    \
-        if (!(cond))                                        \
-            return ::sdm::fail(SDM_E_INVALID, __VA_ARGS__); \
-    } while (0)
-
 static void destroy_ctx(sdm_ctx *c)
 {
     if (!c)
@@ -79,6 +60,8 @@ static void destroy_ctx(sdm_ctx *c)
         (void)hipFree(c->tmp_u32);
     if (c->tile_cnt)
         (void)hipFree(c->tile_cnt);
+    if (c->mlp_part)
+        (void)hipFree(c->mlp_part);
     delete c;
 }
 
@@ -235,6 +218,252 @@ int sdm_step(sdm_ctx *ctx, const sdm_state *st, const sdm_step_params *p, hipStr
     }
     engine_run(ctx, plan, in, stream);
     SDM_CATCH
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ batches
+static uint64_t layout_key(const std::vector<sdm_segment> &segs)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over (offset, n_sd)
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(segs.size());
+    for (const auto &g : segs) {
+        mix((uint64_t)g.offset);
+        mix((uint64_t)g.n_sd);
+    }
+    return h;
+}
+
+static int check_batch_state(const sdm_ctx *ctx, const sdm_batch *b, const sdm_state *st,
+                             const sdm_step_params *p)
+{
+    REQUIRE(ctx && b && st && p, "null argument");
+    REQUIRE(st->n_cell == (int32_t)b->segs.size(), "state n_cell != number of segments");
+    REQUIRE(st->n_sd >= b->n_items && st->n_sd <= ctx->n_sd_max, "state n_sd too small");
+    REQUIRE(st->n_attr >= 1 && st->n_attr <= ctx->n_attr_max, "n_attr out of range");
+    REQUIRE(st->attr_stride >= st->n_sd, "attr_stride < n_sd");
+    REQUIRE(st->xi && st->attr && st->idx && st->n_live_dev && st->cell_start,
+            "state pointer is NULL");
+    REQUIRE(((uintptr_t)st->xi & 15) == 0 && ((uintptr_t)st->attr & 15) == 0,
+            "xi and attr must be 16-byte aligned");
+    REQUIRE(std::isfinite(p->dt) && p->dt >= 0, "dt invalid");
+    return SDM_OK;
+}
+
+static void batch_inputs(sdm_batch *b, const sdm_state *st, const sdm_step_params *p,
+                         StepInputs &in)
+{
+    in.n_sd = b->n_items;
+    in.xi = st->xi;
+    in.attr = st->attr;
+    in.n_attr = st->n_attr;
+    in.stride = st->attr_stride;
+    in.cell_id = nullptr;
+    in.seed = p->rng.seed;
+    in.run = 0;
+    in.step = p->rng.step;
+    in.step_dev = p->rng.step_dev;
+    in.step_advance = p->step_advance;
+    in.dt = p->dt;
+    in.idx_out = st->idx;
+    in.cell_start = st->cell_start;
+    in.n_live_out = st->n_live_dev;
+    in.counters = st->counters_dev;
+    in.gamma_out = st->gamma_out;
+    in.slot_cell_local = true;
+    for (int i = 0; i < 4; ++i)
+        in.events[i] = p->events[i];
+}
+
+extern "C" {
+
+int sdm_batch_create(sdm_ctx *ctx, sdm_batch **b, const sdm_segment *segs, int32_t n_seg)
+{
+    REQUIRE(ctx && b && segs, "null argument");
+    *b = nullptr;
+    REQUIRE(n_seg >= 1 && n_seg <= ctx->n_cell_max, "n_seg out of range");
+    int64_t end = 0;
+    for (int32_t i = 0; i < n_seg; ++i) {
+        const sdm_segment &g = segs[i];
+        REQUIRE(g.offset >= end && (g.offset & 1) == 0, "segment %d: offset must be even and "
+                "not overlap the previous segment", i);
+        REQUIRE(g.n_sd >= 0 && g.offset + g.n_sd <= ctx->n_sd_max, "segment %d: size", i);
+        REQUIRE(g.dv > 0 && std::isfinite(g.dv), "segment %d: dv", i);
+        REQUIRE(g.kernel.id >= SDM_KERNEL_GOLOVIN && g.kernel.id <= SDM_KERNEL_MULTIPLICATIVE,
+                "segment %d: kernel id", i);
+        end = g.offset + g.n_sd;
+    }
+    sdm_batch *nb = nullptr;
+    SDM_TRY
+    nb = new sdm_batch();
+    nb->segs.assign(segs, segs + n_seg);
+    nb->n_items = end;
+    nb->schedule = 0;
+    nb->plan = build_batch_plan(ctx, nb->segs, nb->n_items, 0);
+    *b = nb;
+    nb = nullptr;
+    }
+    catch (const ::sdm::HipError &he)
+    {
+        delete nb;
+        return ::sdm::fail(SDM_E_UNSUPPORTED, "%s: %s", he.what, hipGetErrorString(he.e));
+    }
+    catch (...)
+    {
+        delete nb;
+        return ::sdm::fail(SDM_E_NOMEM, "sdm_batch_create failed");
+    }
+    return SDM_OK;
+}
+
+int sdm_batch_destroy(sdm_ctx *ctx, sdm_batch *b)
+{
+    (void)ctx;
+    if (!b)
+        return SDM_OK;
+    (void)hipDeviceSynchronize();
+    free_plan(b->plan);
+    delete b;
+    return SDM_OK;
+}
+
+int sdm_batch_step(sdm_ctx *ctx, sdm_batch *b, const sdm_state *st, const sdm_step_params *p,
+                   hipStream_t stream)
+{
+    if (int rc = check_batch_state(ctx, b, st, p))
+        return rc;
+    SDM_TRY
+    StepInputs in;
+    batch_inputs(b, st, p, in);
+    if (st->gamma_out && st->n_sd >= 2) {
+        const int64_t n = st->n_sd / 2;
+        hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           stream, st->gamma_out, n);
+    }
+    engine_run(ctx, b->plan, in, stream);
+    SDM_CATCH
+}
+
+int sdm_batch_set_schedule(sdm_ctx *ctx, sdm_batch *b, int32_t schedule, int32_t *n_sched)
+{
+    REQUIRE(ctx && b, "null argument");
+    if (n_sched)
+        *n_sched = n_schedules();
+    if (schedule < 0)
+        return SDM_OK;
+    REQUIRE(schedule < n_schedules(), "schedule out of range");
+    SDM_TRY
+    if (schedule != b->schedule) {
+        Plan *np = build_batch_plan(ctx, b->segs, b->n_items, schedule);
+        SDM_HIP(hipDeviceSynchronize());
+        free_plan(b->plan);
+        b->plan = np;
+        b->schedule = schedule;
+    }
+    SDM_CATCH
+}
+
+int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch, const sdm_step_params *p,
+                 int32_t steps, const char *cache_path, int32_t *chosen)
+{
+    if (int rc = check_batch_state(ctx, b, scratch, p))
+        return rc;
+    REQUIRE(steps >= 1, "steps < 1");
+    const uint64_t key = layout_key(b->segs);
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SDM_TRY
+    int best = -1;
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            std::istringstream ls(line);
+            unsigned long long k = 0;
+            int sch = -1;
+            if ((ls >> std::hex >> k >> std::dec >> sch) && k == key && sch >= 0 &&
+                sch < n_schedules())
+                best = sch;
+        }
+    }
+    if (best < 0) {
+        SDM_HIP(hipStreamCreate(&s));
+        SDM_HIP(hipEventCreate(&e0));
+        SDM_HIP(hipEventCreate(&e1));
+        double best_ms = 1e300;
+        for (int sch = 0; sch < n_schedules(); ++sch) {
+            Plan *cand = nullptr;
+            try {
+                cand = build_batch_plan(ctx, b->segs, b->n_items, sch);
+            } catch (const ::sdm::HipError &) {
+                continue;  // this schedule does not fit the plan limits
+            }
+            StepInputs in;
+            batch_inputs(b, scratch, p, in);
+            in.gamma_out = nullptr;
+            in.step_advance = nullptr;
+            for (int i = 0; i < 4; ++i)
+                in.events[i] = nullptr;
+            engine_run(ctx, cand, in, s);  // warm-up
+            SDM_HIP(hipEventRecord(e0, s));
+            for (int t = 0; t < steps; ++t) {
+                in.step = p->rng.step + 1u + (uint32_t)t;
+                engine_run(ctx, cand, in, s);
+            }
+            SDM_HIP(hipEventRecord(e1, s));
+            SDM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SDM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            free_plan(cand);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = sch;
+            }
+        }
+        if (best < 0)
+            throw ::sdm::HipError{hipErrorInvalidValue, "no schedule fits this batch"};
+        if (cache_path) {
+            std::ofstream f(cache_path, std::ios::app);
+            f << std::hex << (unsigned long long)key << std::dec << " " << best << "\n";
+        }
+    }
+    if (best != b->schedule) {
+        Plan *np = build_batch_plan(ctx, b->segs, b->n_items, best);
+        SDM_HIP(hipDeviceSynchronize());
+        free_plan(b->plan);
+        b->plan = np;
+        b->schedule = best;
+    }
+    if (chosen)
+        *chosen = best;
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (s)
+        (void)hipStreamDestroy(s);
+    }
+    catch (const ::sdm::HipError &he)
+    {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+        if (s)
+            (void)hipStreamDestroy(s);
+        return ::sdm::fail(SDM_E_HIP, "%s: %s", he.what, hipGetErrorString(he.e));
+    }
+    catch (...)
+    {
+        return ::sdm::fail(SDM_E_STATE, "sdm_autotune failed");
+    }
+    return SDM_OK;
 }
 
 }  // extern "C"

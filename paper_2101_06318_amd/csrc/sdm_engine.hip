@@ -87,6 +87,7 @@ struct TileArgs {
     const int32_t *cell_bucket_base;
     int32_t B;
     const uint32_t *seg_off;
+    const uint32_t *seg_len;
     const int32_t *seg_run;
     const int32_t *big_cells;
     int32_t n_big;
@@ -334,10 +335,16 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         }
         int seg = 0;
         if (a.seg_off) {
+            // batched runs: slots past a run's length (alignment padding)
+            // belong to no run
             seg = find_seg(a.seg_off, a.n_cell, s[0]);
             cell[0] = cell[1] = seg;
             if (LIST)
                 cell[1] = find_seg(a.seg_off, a.n_cell, s[1]);
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (s[e] - a.seg_off[cell[e]] >= a.seg_len[cell[e]])
+                    live[e] = false;
         } else {
 #pragma unroll
             for (int e = 0; e < 2; ++e)
@@ -1169,13 +1176,14 @@ static int tile_ept_for(int B)
 }
 
 static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
-                        const std::vector<double> &expected)
+                        const std::vector<double> &expected, double bucket_target,
+                        double group_target)
 {
     Plan *p = new Plan();
     try {
+        (void)ctx;
         const int32_t C = (int32_t)expected.size();
-        const double target = ctx->dbg_bucket_target > 0 ? (double)ctx->dbg_bucket_target
-                                                          : BUCKET_TARGET;
+        const double target = bucket_target;
         p->mode = mode;
         p->n_items = n_items;
         p->n_cell = C;
@@ -1217,7 +1225,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                 int nsub = 0, n = 0;
                 while (b < B) {
                     const int ns = 1 << sub_bits[b];
-                    if (n > 0 && (acc + bucket_exp[b] > GROUP_TARGET || n + 1 > MAXB ||
+                    if (n > 0 && (acc + bucket_exp[b] > group_target || n + 1 > MAXB ||
                                   nsub + ns > NSUB))
                         break;
                     acc += bucket_exp[b];
@@ -1301,8 +1309,59 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
     if (it != ctx->plans.end())
         return it->second;
     std::vector<double> exp(n_cell, expected_per_cell);
-    Plan *p = build_plan(ctx, mode, n_items, exp);
+    const double bt = ctx->dbg_bucket_target > 0 ? (double)ctx->dbg_bucket_target : BUCKET_TARGET;
+    Plan *p = build_plan(ctx, mode, n_items, exp, bt, GROUP_TARGET);
     ctx->plans[key] = p;
+    return p;
+}
+
+// Schedules the batch autotuner chooses from: (expected SDs per key bucket,
+// expected SDs per group).  Results never depend on the choice.
+static const double kSchedules[][2] = {
+    {4096.0, 4096.0}, {2048.0, 4096.0}, {1024.0, 4096.0},
+    {4096.0, 3072.0}, {2048.0, 2048.0}, {1024.0, 2048.0},
+};
+int n_schedules() { return (int)(sizeof(kSchedules) / sizeof(kSchedules[0])); }
+
+Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64_t n_items,
+                       int schedule)
+{
+    std::vector<double> exp(segs.size());
+    for (size_t i = 0; i < segs.size(); ++i)
+        exp[i] = (double)segs[i].n_sd;
+    double bt = kSchedules[schedule][0], gt = kSchedules[schedule][1];
+    if (ctx->dbg_bucket_target > 0)
+        bt = (double)ctx->dbg_bucket_target;
+    Plan *p = build_plan(ctx, MODE_FUSED, n_items, exp, bt, gt);
+    try {
+        const int C = (int)segs.size();
+        std::vector<uint32_t> off(C + 1), len(C);
+        std::vector<int32_t> run(C), kidx(C);
+        std::vector<double> dv(C);
+        std::vector<KernelDesc> kernels(C);
+        for (int c = 0; c < C; ++c) {
+            off[c] = (uint32_t)segs[c].offset;
+            len[c] = (uint32_t)segs[c].n_sd;
+            run[c] = (int32_t)segs[c].run;
+            dv[c] = segs[c].dv;
+            kidx[c] = c;
+            kernels[c].id = segs[c].kernel.id;
+            kernels[c].reserved = 0;
+            for (int i = 0; i < 4; ++i)
+                kernels[c].p[i] = segs[c].kernel.p[i];
+        }
+        off[C] = (uint32_t)n_items;
+        p->seg_off = upload(p, off);
+        p->seg_len = upload(p, len);
+        p->seg_run = upload(p, run);
+        p->seg_kernel = upload(p, kidx);
+        p->seg_dv = upload(p, dv);
+        p->kernels = upload(p, kernels);
+        SDM_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        free_plan(p);
+        throw;
+    }
     return p;
 }
 
@@ -1349,6 +1408,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.cell_bucket_base = p->cell_bucket_base;
     ta.B = p->B;
     ta.seg_off = p->seg_off;
+    ta.seg_len = p->seg_len;
     ta.seg_run = p->seg_run;
     ta.big_cells = p->big_cells;
     ta.n_big = p->n_big;

@@ -31,6 +31,31 @@ struct HipError {
             throw ::sdm::HipError{_e, #call};                                \
     } while (0)
 
+// Entry-point bodies: exceptions never cross the C boundary; every
+// failure becomes a status code with a message.
+#define SDM_TRY try {
+#define SDM_CATCH                                                                     \
+    }                                                                                 \
+    catch (const ::sdm::HipError &he)                                                 \
+    {                                                                                 \
+        return ::sdm::fail(SDM_E_HIP, "%s: %s", he.what, hipGetErrorString(he.e));    \
+    }                                                                                 \
+    catch (const std::bad_alloc &)                                                    \
+    {                                                                                 \
+        return ::sdm::fail(SDM_E_NOMEM, "host allocation failed");                    \
+    }                                                                                 \
+    catch (...)                                                                       \
+    {                                                                                 \
+        return ::sdm::fail(SDM_E_STATE, "unexpected exception");                      \
+    }                                                                                 \
+    return SDM_OK;
+
+#define REQUIRE(cond, ...)                                  \
+    do {                                                    \
+        if (!(cond))                                        \
+            return ::sdm::fail(SDM_E_INVALID, __VA_ARGS__); \
+    } while (0)
+
 // ------------------------------------------------------------ engine plan
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
@@ -73,6 +98,7 @@ struct Plan {
     int32_t *group_first = nullptr;       // [G+1]
     // per-cell run description (batched plans); null for single-run plans
     uint32_t *seg_off = nullptr;          // [C+1] SD slot offsets
+    uint32_t *seg_len = nullptr;          // [C] SD slots of each run
     int32_t *seg_run = nullptr;           // [C]
     int32_t *seg_kernel = nullptr;        // [C] index into kernel table
     double *seg_dv = nullptr;             // [C]
@@ -113,6 +139,13 @@ struct PlanKey {
 
 }  // namespace sdm
 
+struct sdm_batch {
+    std::vector<sdm_segment> segs;
+    int64_t n_items = 0;       // SD slots covered (last offset + n_sd, rounded up to even)
+    int schedule = 0;
+    sdm::Plan *plan = nullptr;
+};
+
 struct sdm_ctx {
     int device = 0;
     int64_t n_sd_max = 0;
@@ -124,6 +157,8 @@ struct sdm_ctx {
     std::map<sdm::PlanKey, sdm::Plan *> plans;
     int32_t dbg_bucket_target = 0;     // testing: expected SDs per bucket
     int32_t dbg_group_cap = -1;        // testing: force the global-memory sort
+    float *mlp_part = nullptr;         // [mlp_part_rows][n_params] backward partial sums
+    int32_t mlp_part_rows = 0;
 };
 
 namespace sdm {
@@ -166,5 +201,10 @@ struct StepInputs {
 };
 
 void engine_run(sdm_ctx *ctx, Plan *plan, const StepInputs &in, hipStream_t stream);
+
+// batched ensembles (sdm_engine.hip)
+int n_schedules();
+Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64_t n_items,
+                       int schedule);
 
 }  // namespace sdm

@@ -297,29 +297,6 @@ __global__ void k_reassign(int32_t *cell_id, int64_t n_sd, int32_t n_cell, uint6
 }  // namespace
 
 // ====================================================================== ABI
-#define SDM_TRY try {
-#define SDM_CATCH                                                                     \
-    }                                                                                 \
-    catch (const ::sdm::HipError &he)                                                 \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_HIP, "%s: %s", he.what, hipGetErrorString(he.e));    \
-    }                                                                                 \
-    catch (const std::bad_alloc &)                                                    \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_NOMEM, "host allocation failed");                    \
-    }                                                                                 \
-    catch (...)                                                                       \
-    {                                                                                 \
-        return ::sdm::fail(SDM_E_STATE, "unexpected exception");                      \
-    }                                                                                 \
-    return SDM_OK;
-
-#define REQUIRE(cond, ...)                                \
-    do {                                                  \
-        if (!(cond))                                      \
-            return ::sdm::fail(SDM_E_INVALID, __VA_ARGS__); \
-    } while (0)
-
 static int check_kernel(const sdm_kernel *k)
 {
     if (!k)
