@@ -78,6 +78,7 @@ enum { SDM_CNT_PAIRS = 0,      /* flagged pairs visited                      */
        SDM_CNT_CAPPED = 2,     /* gamma-tilde < gamma (eq. 4 cap active)     */
        SDM_CNT_ZEROED = 3,     /* eq. (6) split with xi_k = 1: xi_j -> 0     */
        SDM_CNT_GAMMA_GE2 = 4,  /* pairs with gamma >= 2                      */
+       SDM_CNT_FALLBACK = 5,   /* cells outside the surrogate's input hull   */
        SDM_CNT_N = 8 };
 
 typedef struct sdm_ctx sdm_ctx;
@@ -321,6 +322,94 @@ int sdm_moments(sdm_ctx *ctx, double *M, const uint64_t *xi,
  * of two.  cell_id: device int32[n_sd], out. */
 int sdm_reassign(sdm_ctx *ctx, int32_t *cell_id, int64_t n_sd, int32_t n_cell,
                  const sdm_rng *rng, hipStream_t stream);
+
+/* --------------------------------------------------- moment surrogate */
+/* A learned model of one cell's coagulation over dt in terms of its bulk
+ * moments only (the paper's outlook, Sec. 5: a coupled fluid solver needs
+ * statistical moments of the spectrum, not the particles).
+ *
+ * Network: x[5] -> 128 -> 128 -> 128 -> y[3]; layer l computes
+ * z = W_l a + b_l, GELU(z) = z Phi(z) (exact erf form) after each hidden
+ * layer, linear output.  x = standardised (log M0, log M1, log M2, dt,
+ * kernel id) of a cell; y = standardised relative moment tendencies
+ * (M_k(t + dt) - M_k(t)) / (M_k(t) dt).  Arithmetic: every matmul takes
+ * bfloat16 operands (weights, x, activations, back-propagated errors,
+ * rounded to nearest even) on the matrix cores with float32 accumulation;
+ * bias adds, GELU, its derivative, loss, gradients and Adam are float32.
+ *
+ * Parameters: one flat float32 vector of SDM_MLP_N_PARAMS entries in the
+ * order W1, b1, W2, b2, W3, b3, W4, b4, each W row-major [out][in]. */
+#define SDM_MLP_N_PARAMS 34179
+#define SDM_MLP_PACKED_BYTES 151552   /* bf16 weights in the kernels' order */
+#define SDM_MLP_CACHE_FLOATS_PER_ROW 384
+
+typedef struct {
+    float *params;           /* device float[SDM_MLP_N_PARAMS]: fp32 masters */
+    void  *packed;           /* device, SDM_MLP_PACKED_BYTES, 16-B aligned:  */
+                             /* bf16 copy written by sdm_mlp_pack/_adam      */
+} sdm_mlp;
+
+typedef struct {
+    float *m;                /* device float[SDM_MLP_N_PARAMS], start at 0   */
+    float *v;                /* device float[SDM_MLP_N_PARAMS], start at 0   */
+} sdm_mlp_opt;
+
+typedef struct {
+    double  lr, beta1, beta2, eps;  /* 1 - beta is formed in double, then */
+                                    /* rounded to float for the kernel    */
+    int32_t t;               /* 1-based step number (bias correction)        */
+    int32_t reserved;
+} sdm_adam_hp;
+
+/* Rounds the fp32 masters to bf16 into w->packed.  Call after writing
+ * w->params (sdm_mlp_adam repacks by itself). */
+int sdm_mlp_pack(sdm_ctx *ctx, const sdm_mlp *w, hipStream_t stream);
+
+/* y[B][3] = network(x[B][5]) (device float, row-major).  cache: NULL for
+ * inference, or device float[ceil(B/16)*16 * SDM_MLP_CACHE_FLOATS_PER_ROW]
+ * receiving the hidden pre-activations for sdm_mlp_backward (layout private
+ * to the library).  B = 0 is a no-op. */
+int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_t B,
+                    const sdm_mlp *w, hipStream_t stream);
+
+/* grad[SDM_MLP_N_PARAMS] (device float, overwritten) = d(sum_b,j dy[b][j]
+ * y[b][j]) / d params, for the batch of the forward call that filled
+ * cache from x.  Sums over the batch in a fixed order (deterministic).  The
+ * first call with a batch needing more partial-sum rows than any before
+ * allocates (blocking; not capturable). */
+int sdm_mlp_backward(sdm_ctx *ctx, float *grad, const float *dy, const float *x,
+                     const float *cache, int64_t B, const sdm_mlp *w, hipStream_t stream);
+
+/* Mean-squared error over the B*3 outputs: dy = 2 (y - t) / (3B) and
+ * *loss = sum (y - t)^2 / (3B) (device floats; loss may be NULL). */
+int sdm_mlp_mse(sdm_ctx *ctx, float *dy, float *loss, const float *y, const float *t,
+                int64_t B, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) on w->params from grad, updating opt->m,
+ * opt->v, then repacking w->packed. */
+int sdm_mlp_adam(sdm_ctx *ctx, const sdm_mlp *w, const sdm_mlp_opt *opt, const float *grad,
+                 const sdm_adam_hp *hp, hipStream_t stream);
+
+/* Out-of-distribution test: fallback[b] = 1 when any feature x[b][i] lies
+ * outside [lo[i], hi[i]] or is NaN (the per-feature box of the training
+ * inputs), else 0.  lo, hi: host float[5] (copied).  counters_dev
+ * (optional) gets the number of fallback rows added at SDM_CNT_FALLBACK. */
+int sdm_hull_check(sdm_ctx *ctx, uint8_t *fallback, uint64_t *counters_dev, const float *x,
+                   int64_t B, const float *lo, const float *hi, hipStream_t stream);
+
+/* Surrogate input of n cells: x[c] = ((log M0, log M1, log M2, dt,
+ * kernel_id) - mean) / std with M: device double[n][3] (sdm_moments
+ * layout), x: device float[n][5]; mean, std: host float[5] (copied). */
+int sdm_mlp_features(sdm_ctx *ctx, float *x, const double *M, int64_t n, double dt,
+                     int32_t kernel_id, const float *mean, const float *std,
+                     hipStream_t stream);
+
+/* Surrogate update of n cells: M[c][k] *= 1 + dt (y[c][k] std[k] + mean[k])
+ * for cells with fallback[c] == 0 (fallback may be NULL); others are left
+ * for the particle step.  M: device double[n][3]; y: device float[n][3];
+ * mean, std: host float[3] (target standardisation, copied). */
+int sdm_mlp_apply(sdm_ctx *ctx, double *M, const float *y, const uint8_t *fallback, int64_t n,
+                  double dt, const float *mean, const float *std, hipStream_t stream);
 
 #ifdef __cplusplus
 }

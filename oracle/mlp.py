@@ -167,14 +167,30 @@ def hull_fallback(x, lo, hi):
 
 def features(M, dt, kernel_id, mean, std):
     """Standardised features of cells with moments M [n][3] (float64):
-    ((log M0, log M1, log M2, dt, kernel id) - mean) / std, float32."""
+    ((log M0, log M1, log M2, dt, kernel id) - mean) / std in float64 with
+    mean and std given as float32 values, rounded to float32."""
     M = np.asarray(M, np.float64)
     raw = np.stack([np.log(M[:, 0]), np.log(M[:, 1]), np.log(M[:, 2]),
                     np.full(len(M), float(dt)), np.full(len(M), float(kernel_id))], axis=1)
-    return ((raw - np.asarray(mean, np.float64)) / np.asarray(std, np.float64)).astype(np.float32)
+    mean = np.asarray(mean, np.float32).astype(np.float64)
+    std = np.asarray(std, np.float32).astype(np.float64)
+    return ((raw - mean) / std).astype(np.float32)
 
 
 def tendencies(M0, M1, dt):
     """Relative moment tendencies (M1_k - M0_k) / (M0_k dt)."""
     M0 = np.asarray(M0, np.float64)
     return (np.asarray(M1, np.float64) - M0) / (M0 * dt)
+
+
+def apply(M, y, fallback, dt, mean, std):
+    """Surrogate update of the moments: T = y std + mean (de-standardised
+    relative tendency), M_k <- M_k (1 + dt T_k) for cells that do not fall
+    back; float64, evaluated in that order."""
+    M = np.array(M, np.float64, copy=True)
+    y = np.asarray(y, np.float32).astype(np.float64)
+    tend = y * np.asarray(std, np.float32).astype(np.float64) + np.asarray(mean, np.float32).astype(np.float64)
+    new = M * (1.0 + float(dt) * tend)
+    keep = np.ones(len(M), bool) if fallback is None else (np.asarray(fallback) == 0)
+    M[keep] = new[keep]
+    return M

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsdm.so")
 SDM_OK = 0
 STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP = range(5)
 KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE = range(4)
-CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2 = range(5)
+CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2, CNT_FALLBACK = range(6)
 N_COUNTERS = 8
 
 
@@ -51,6 +51,19 @@ class StepParamsC(C.Structure):
     _fields_ = [("dt", C.c_double), ("dv_per_cell", C.c_void_p), ("dv", C.c_double),
                 ("kernel", Kernel), ("rng", Rng), ("step_advance", C.c_void_p),
                 ("expected_per_cell", C.c_double), ("events", C.c_void_p * 4)]
+
+
+class MlpC(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("packed", C.c_void_p)]
+
+
+class MlpOptC(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("v", C.c_void_p)]
+
+
+class AdamHpC(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("t", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Segment(C.Structure):
@@ -94,7 +107,20 @@ SIGNATURES = {
                             C.c_char_p, C.POINTER(_I32)]),
     "sdm_moments": (_INT, [_P, _P, _P, _P, _P, _P, _I32, _P, _D, _P]),
     "sdm_reassign": (_INT, [_P, _P, _I64, _I32, C.POINTER(Rng), _P]),
+    "sdm_mlp_pack": (_INT, [_P, C.POINTER(MlpC), _P]),
+    "sdm_mlp_forward": (_INT, [_P, _P, _P, _P, _I64, C.POINTER(MlpC), _P]),
+    "sdm_mlp_backward": (_INT, [_P, _P, _P, _P, _P, _I64, C.POINTER(MlpC), _P]),
+    "sdm_mlp_mse": (_INT, [_P, _P, _P, _P, _P, _I64, _P]),
+    "sdm_mlp_adam": (_INT, [_P, C.POINTER(MlpC), C.POINTER(MlpOptC), _P, C.POINTER(AdamHpC),
+                            _P]),
+    "sdm_hull_check": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "sdm_mlp_features": (_INT, [_P, _P, _P, _I64, _D, _I32, _P, _P, _P]),
+    "sdm_mlp_apply": (_INT, [_P, _P, _P, _P, _I64, _D, _P, _P, _P]),
 }
+
+MLP_N_PARAMS = 34179
+MLP_PACKED_BYTES = 151552
+MLP_CACHE_FLOATS_PER_ROW = 384
 
 _lib = None
 
@@ -256,6 +282,47 @@ class Context:
         _check(lib().sdm_reassign(self._h, _ptr(cell_id), int(n_sd), int(n_cell), C.byref(r),
                                   _stream(stream)))
 
+    # ------------------------------------------------ moment surrogate
+    def mlp_pack(self, net, stream=None):
+        _check(lib().sdm_mlp_pack(self._h, C.byref(net.c), _stream(stream)))
+
+    def mlp_forward(self, y, x, net, cache=None, stream=None):
+        _check(lib().sdm_mlp_forward(self._h, _ptr(y), _ptr(cache), _ptr(x), int(x.shape[0]),
+                                     C.byref(net.c), _stream(stream)))
+
+    def mlp_backward(self, grad, dy, x, cache, net, stream=None):
+        _check(lib().sdm_mlp_backward(self._h, _ptr(grad), _ptr(dy), _ptr(x), _ptr(cache),
+                                      int(x.shape[0]), C.byref(net.c), _stream(stream)))
+
+    def mlp_mse(self, dy, loss, y, t, stream=None):
+        _check(lib().sdm_mlp_mse(self._h, _ptr(dy), _ptr(loss), _ptr(y), _ptr(t),
+                                 int(y.shape[0]), _stream(stream)))
+
+    def mlp_adam(self, net, m, v, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+        opt = MlpOptC(_ptr(m), _ptr(v))
+        hp = AdamHpC(lr, beta1, beta2, eps, int(t), 0)
+        _check(lib().sdm_mlp_adam(self._h, C.byref(net.c), C.byref(opt), _ptr(grad),
+                                  C.byref(hp), _stream(stream)))
+
+    def hull_check(self, fallback, x, lo, hi, counters=None, stream=None):
+        lo_a = (C.c_float * 5)(*[float(v) for v in lo])
+        hi_a = (C.c_float * 5)(*[float(v) for v in hi])
+        _check(lib().sdm_hull_check(self._h, _ptr(fallback), _ptr(counters), _ptr(x),
+                                    int(x.shape[0]), lo_a, hi_a, _stream(stream)))
+
+    def mlp_features(self, x, M, dt, kernel_id, mean, std, stream=None):
+        m_a = (C.c_float * 5)(*[float(v) for v in mean])
+        s_a = (C.c_float * 5)(*[float(v) for v in std])
+        _check(lib().sdm_mlp_features(self._h, _ptr(x), _ptr(M), int(M.shape[0]), float(dt),
+                                      int(kernel_id), m_a, s_a, _stream(stream)))
+
+    def mlp_apply(self, M, y, dt, mean, std, fallback=None, stream=None):
+        m_a = (C.c_float * 3)(*[float(v) for v in mean])
+        s_a = (C.c_float * 3)(*[float(v) for v in std])
+        _check(lib().sdm_mlp_apply(self._h, _ptr(M), _ptr(y), _ptr(fallback), int(M.shape[0]),
+                                   float(dt), m_a, s_a, _stream(stream)))
+
     # ------------------------------------------------ fused timestep
     def _state(self, st):
         s = StateC()
@@ -371,3 +438,22 @@ class State:
         self.counters = torch.zeros(N_COUNTERS, dtype=torch.uint64, device=device)
         self.gamma_out = (torch.zeros(max(self.n_sd // 2, 1), dtype=torch.float64, device=device)
                           if want_gamma else None)
+
+
+class Mlp:
+    """Device parameters of the moment surrogate: fp32 masters (flat
+    W1, b1, ..., W4, b4, W row-major [out][in]) and their packed bf16 copy."""
+
+    def __init__(self, ctx, params, device="cuda"):
+        import torch
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(device).contiguous()
+        assert self.params.numel() == MLP_N_PARAMS
+        self.packed = torch.empty(MLP_PACKED_BYTES // 4, dtype=torch.int32, device=device)
+        self.c = MlpC(_ptr(self.params), _ptr(self.packed))
+        ctx.mlp_pack(self)
+
+    @staticmethod
+    def cache_for(B, device="cuda"):
+        import torch
+        rows = (int(B) + 15) // 16 * 16
+        return torch.empty(rows * MLP_CACHE_FLOATS_PER_ROW, dtype=torch.float32, device=device)

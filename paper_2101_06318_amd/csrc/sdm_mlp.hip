@@ -1,0 +1,774 @@
+// Moment-surrogate network on the gfx950 matrix cores.
+//
+// The network (5 -> 128 -> 128 -> 128 -> 3, GELU) is small enough that a
+// whole forward or backward pass of a 16-sample tile stays in one wave's
+// registers.  Every matmul is v_mfma_f32_16x16x32_bf16 in transposed form,
+// Z^T = W A^T: the weights are the M x K operand and the activations of 16
+// samples the K x N operand.  The 16x16 result of one output tile leaves
+// lane (r, g) = (lane % 16, lane / 16) holding neurons 16t + 4g + e
+// (e = 0..3) of sample r, which is almost the layout the next matmul needs
+// for its K x N operand (lane (r, g) holding 8 consecutive K slots
+// 8g..8g+7 of sample r).  Since the contraction may visit K in any order,
+// the K slots of K-step q are mapped to neurons by
+//   slot 8g + e  ->  32q + 4g + e        (e < 4, from output tile 2q)
+//   slot 8g + e  ->  32q + 16 + 4g + e-4 (e >= 4, from output tile 2q+1)
+// and the weights are stored ("packed") with the same permutation, so the
+// activations never leave the registers between layers.
+//
+// Weight gradients dW = dZ^T A sum over samples, a different operand
+// layout; there the workgroup stages dZ^T and A^T of its 64 samples in LDS
+// and each wave takes a share of the output tiles.  Per-workgroup partial
+// sums are reduced in a fixed order by a second kernel (deterministic).
+#include <math.h>
+
+#include "sdm_internal.h"
+
+using namespace sdm;
+
+namespace {
+
+constexpr int NIN = 5, NH = 128, NOUT = 3;
+constexpr int OFF_W1 = 0, OFF_B1 = 640, OFF_W2 = 768, OFF_B2 = 17152, OFF_W3 = 17280,
+              OFF_B3 = 33664, OFF_W4 = 33792, OFF_B4 = 34176, NPARAM = 34179;
+static_assert(NPARAM == SDM_MLP_N_PARAMS, "parameter count");
+
+// Packed fragments: 64 lanes x 8 bf16 (1 KiB) each.
+//   F1 [t]     layer 1, K = 5 input features padded to 32 (natural order)
+//   F2 [t][q]  layer 2 (permuted K)      F3 [t][q] layer 3
+//   F4 [q]     layer 4, M = 3 outputs padded to 16
+//   B4 [t]     W4^T for dH3 = W4^T dZ4 (K = 3 padded to 32, natural order)
+//   B3 [t][q]  W3^T for dH2               B2 [t][q] W2^T for dH1
+constexpr int FR_F1 = 0, FR_F2 = 8, FR_F3 = 40, FR_F4 = 72, FR_B4 = 76, FR_B3 = 84,
+              FR_B2 = 116, FR_N = 148, FWD_FRAGS = 76;
+static_assert(FR_N * 1024 == SDM_MLP_PACKED_BYTES, "packed size");
+static_assert(3 * 8 * 64 * 4 == 16 * SDM_MLP_CACHE_FLOATS_PER_ROW, "cache tile size");
+
+constexpr int BWD_CHUNK = 64;      // samples per backward workgroup pass
+constexpr int BWD_ROW = 72;        // LDS row stride (bf16): 64 samples + 8 pad
+constexpr int PART_ROWS_MAX = 128; // backward workgroups (partial-sum rows)
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+
+__device__ inline f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ inline uint32_t bf16_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ inline uint32_t pack2(float lo, float hi)
+{
+    return bf16_bits(lo) | (bf16_bits(hi) << 16);
+}
+
+__device__ inline float gelu(float z)
+{
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+__device__ inline float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * (expf(-0.5f * z * z) * 0.39894228040143268f);
+}
+
+__device__ inline int perm32(int p)
+{
+    const int g = p >> 3, e = p & 7;
+    return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4);
+}
+
+// Master weight behind packed bf16 element i (0 for padding).
+__device__ inline float pack_source(const float *P, int i)
+{
+    const int f = i >> 9, l = (i >> 3) & 63, e = i & 7;
+    const int r = l & 15, p = 8 * (l >> 4) + e;
+    if (f < FR_F2)
+        return p < NIN ? P[OFF_W1 + (16 * f + r) * NIN + p] : 0.0f;
+    if (f < FR_F3) {
+        const int t = (f - FR_F2) >> 2, q = (f - FR_F2) & 3;
+        return P[OFF_W2 + (16 * t + r) * NH + 32 * q + perm32(p)];
+    }
+    if (f < FR_F4) {
+        const int t = (f - FR_F3) >> 2, q = (f - FR_F3) & 3;
+        return P[OFF_W3 + (16 * t + r) * NH + 32 * q + perm32(p)];
+    }
+    if (f < FR_B4) {
+        const int q = f - FR_F4;
+        return r < NOUT ? P[OFF_W4 + r * NH + 32 * q + perm32(p)] : 0.0f;
+    }
+    if (f < FR_B3)
+        return p < NOUT ? P[OFF_W4 + p * NH + 16 * (f - FR_B4) + r] : 0.0f;
+    if (f < FR_B2) {
+        const int t = (f - FR_B3) >> 2, q = (f - FR_B3) & 3;
+        return P[OFF_W3 + (32 * q + perm32(p)) * NH + 16 * t + r];
+    }
+    const int t = (f - FR_B2) >> 2, q = (f - FR_B2) & 3;
+    return P[OFF_W2 + (32 * q + perm32(p)) * NH + 16 * t + r];
+}
+
+__global__ void k_mlp_pack(uint32_t *__restrict__ packed, const float *__restrict__ P)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;  // one 32-bit word = 2 bf16
+    if (w < FR_N * 256)
+        packed[w] = pack2(pack_source(P, 2 * w), pack_source(P, 2 * w + 1));
+}
+
+// Bias, GELU and bf16 rounding of output tile t of a hidden layer; the
+// rounded activations go to K-step t/2 of the next layer's operand.
+template <int S, bool TRAIN>
+__device__ inline void hidden_epilogue(const f32x4 (&acc)[S], int t, int layer,
+                                       const float *__restrict__ sb, u32x4 (&out)[S][4],
+                                       float *__restrict__ cache, int64_t tile0, int64_t n_tiles,
+                                       int lane)
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        float h[4];
+        f32x4 z;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            z[e] = acc[j][e] + sb[layer * NH + 16 * t + 4 * g + e];
+            h[e] = gelu(z[e]);
+        }
+        if (TRAIN && tile0 + j < n_tiles)
+            *(f32x4 *)(cache + (((tile0 + j) * 3 + layer) * 8 + t) * 256 + lane * 4) = z;
+        const int q = t >> 1;
+        if (t & 1) {
+            out[j][q][2] = pack2(h[0], h[1]);
+            out[j][q][3] = pack2(h[2], h[3]);
+        } else {
+            out[j][q][0] = pack2(h[0], h[1]);
+            out[j][q][1] = pack2(h[2], h[3]);
+        }
+    }
+}
+
+template <int S, bool TRAIN>
+__device__ inline void hidden_layer(const u32x4 *__restrict__ frags, int layer,
+                                    const float *__restrict__ sb, const u32x4 (&in)[S][4],
+                                    u32x4 (&out)[S][4], float *__restrict__ cache, int64_t tile0,
+                                    int64_t n_tiles, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        f32x4 acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4 a = frags[(t * 4 + q) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                acc[j] = mfma(a, in[j][q], acc[j]);
+        }
+        hidden_epilogue<S, TRAIN>(acc, t, layer, sb, out, cache, tile0, n_tiles, lane);
+    }
+}
+
+// Forward pass.  Workgroup: 4 waves; wave w takes S consecutive 16-sample
+// tiles.  The forward fragments (76 KiB) and biases are staged in LDS.
+template <int S, bool TRAIN>
+__global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
+                                                     float *__restrict__ cache,
+                                                     const float *__restrict__ x, int64_t B,
+                                                     const u32x4 *__restrict__ packed,
+                                                     const float *__restrict__ P)
+{
+    __shared__ u32x4 sw[FWD_FRAGS * 64];
+    __shared__ float sb[3 * NH + 4];
+    for (int i = threadIdx.x; i < FWD_FRAGS * 64; i += 256)
+        sw[i] = packed[i];
+    for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 256)
+        sb[i] = P[i < NH ? OFF_B1 + i
+                  : i < 2 * NH ? OFF_B2 + (i - NH)
+                  : i < 3 * NH ? OFF_B3 + (i - 2 * NH)
+                               : OFF_B4 + (i - 3 * NH)];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const int64_t n_tiles = (B + 15) / 16;
+    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + w) * S;
+    if (tile0 >= n_tiles)
+        return;
+
+    u32x4 ha[S][4], hb[S][4];
+    // layer 1: the K x N operand is x itself (features 8g..8g+7 of sample r)
+    u32x4 bx[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int64_t s = (tile0 + j) * 16 + r;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            v[e] = (k < NIN && s < B) ? x[s * NIN + k] : 0.0f;
+        }
+        bx[j] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const u32x4 a = sw[(FR_F1 + t) * 64 + lane];
+        f32x4 acc[S];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            acc[j] = mfma(a, bx[j], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        hidden_epilogue<S, TRAIN>(acc, t, 0, sb, ha, cache, tile0, n_tiles, lane);
+    }
+    hidden_layer<S, TRAIN>(sw + FR_F2 * 64, 1, sb, ha, hb, cache, tile0, n_tiles, lane);
+    hidden_layer<S, TRAIN>(sw + FR_F3 * 64, 2, sb, hb, ha, cache, tile0, n_tiles, lane);
+    // layer 4: rows 0..2 of the 16-row output tile are the outputs
+    f32x4 acc[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+        acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const u32x4 a = sw[(FR_F4 + q) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            acc[j] = mfma(a, ha[j][q], acc[j]);
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int64_t s = (tile0 + j) * 16 + r;
+            if (s < B) {
+#pragma unroll
+                for (int e = 0; e < NOUT; ++e)
+                    y[s * NOUT + e] = acc[j][e] + sb[3 * NH + e];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward
+__device__ inline float sum16(float v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    return v;
+}
+
+__device__ inline void put(float *p, bool first, float v)
+{
+    *p = first ? v : *p + v;
+}
+
+__device__ inline u32x4 lds_frag(const uint16_t *base, int row, int col)
+{
+    return *(const u32x4 *)(base + row * BWD_ROW + col);
+}
+
+// dW tile (rows 16 tn.., cols 16 tk..) = sum over the chunk's 64 samples of
+// G[n][s] H[k][s]; lane (r, g) receives rows 16 tn + 4g + e, column 16 tk + r.
+__device__ inline f32x4 dw_tile(const uint16_t *G, const uint16_t *H, int tn, int tk, int lane)
+{
+    const int r = lane & 15, g = lane >> 4;
+    f32x4 acc{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < BWD_CHUNK; kk += 32)
+        acc = mfma(lds_frag(G, 16 * tn + r, kk + 8 * g), lds_frag(H, 16 * tk + r, kk + 8 * g), acc);
+    return acc;
+}
+
+// Writes the bf16 transpose of a 128 x 16 register tile set (lane (r, g)
+// holding v[t][e] for feature 16t + 4g + e of sample column col) into an
+// LDS [feature][sample] buffer.
+__device__ inline void stage_t(uint16_t *buf, const f32x4 (&v)[8], int col, int g)
+{
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            buf[(16 * t + 4 * g + e) * BWD_ROW + col] = (uint16_t)bf16_bits(v[t][e]);
+}
+
+__device__ inline void load_z(f32x4 (&z)[8], const float *__restrict__ cache, int64_t tile,
+                              bool valid, int layer, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        z[t] = valid ? *(const f32x4 *)(cache + ((tile * 3 + layer) * 8 + t) * 256 + lane * 4)
+                     : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+// Operand of the next backward matmul from dZ tiles (same slot permutation
+// as the forward pass).
+__device__ inline void to_operand(u32x4 (&op)[4], const f32x4 (&d)[8])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        op[q] = u32x4{pack2(d[2 * q][0], d[2 * q][1]), pack2(d[2 * q][2], d[2 * q][3]),
+                      pack2(d[2 * q + 1][0], d[2 * q + 1][1]),
+                      pack2(d[2 * q + 1][2], d[2 * q + 1][3])};
+}
+
+// Backward pass over chunks of 64 samples (4 tiles, one per wave); each
+// workgroup accumulates its chunks into its own row of `part`.
+__global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
+                                                      const float *__restrict__ dy,
+                                                      const float *__restrict__ x,
+                                                      const float *__restrict__ cache, int64_t B,
+                                                      const u32x4 *__restrict__ packed,
+                                                      int64_t n_chunks)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t G[NH * BWD_ROW];
+    __shared__ __attribute__((aligned(16))) uint16_t H[NH * BWD_ROW];
+    __shared__ float bsum[4][NH];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const int col = 16 * w + r;
+    const int64_t n_tiles = (B + 15) / 16;
+    float *prow = part + (int64_t)blockIdx.x * NPARAM;
+
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        const bool first = chunk == blockIdx.x;
+        const int64_t tile = chunk * 4 + w;
+        const bool tv = tile < n_tiles;
+        const int64_t s = tile * 16 + r;
+
+        // ---- layer 4: dZ4 = dy
+        float d4[NOUT];
+#pragma unroll
+        for (int e = 0; e < NOUT; ++e)
+            d4[e] = s < B ? dy[s * NOUT + e] : 0.0f;
+        const u32x4 op4 = g == 0 ? u32x4{pack2(d4[0], d4[1]), pack2(d4[2], 0.0f), 0u, 0u}
+                                 : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int n = 4 * g + e;
+            G[n * BWD_ROW + col] = n < NOUT ? (uint16_t)bf16_bits(d4[n < NOUT ? n : 0]) : 0;
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int e = 0; e < NOUT; ++e) {
+                const float t = sum16(d4[e]);
+                if (r == 0)
+                    bsum[w][e] = t;
+            }
+        }
+        f32x4 z[8], h[8], dz[8];
+        load_z(z, cache, tile, tv, 2, lane);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                h[t][e] = gelu(z[t][e]);
+        stage_t(H, h, col, g);
+        __syncthreads();
+        // dW4 (rows 0..2 of tile 0), tiles over k: tk = w, w + 4
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int tk = w + 4 * i;
+            const f32x4 a = dw_tile(G, H, 0, tk, lane);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * g + e < NOUT)
+                    put(prow + OFF_W4 + (4 * g + e) * NH + 16 * tk + r, first, a[e]);
+        }
+        if (threadIdx.x < NOUT)
+            put(prow + OFF_B4 + threadIdx.x, first,
+                ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
+                    bsum[3][threadIdx.x]);
+        // dH3 = W4^T dZ4, dZ3 = dH3 * GELU'(z3)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f32x4 a = mfma(packed[(FR_B4 + t) * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                dz[t][e] = a[e] * gelu_grad(z[t][e]);
+        }
+        __syncthreads();
+
+        // ---- layers 3 and 2
+#pragma unroll 1
+        for (int layer = 2; layer >= 1; --layer) {
+            const int offW = layer == 2 ? OFF_W3 : OFF_W2;
+            const int offB = layer == 2 ? OFF_B3 : OFF_B2;
+            const int frB = layer == 2 ? FR_B3 : FR_B2;
+            u32x4 op[4];
+            to_operand(op, dz);
+            stage_t(G, dz, col, g);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = sum16(dz[t][e]);
+                    if (r == 0)
+                        bsum[w][16 * t + 4 * g + e] = v;
+                }
+            load_z(z, cache, tile, tv, layer - 1, lane);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    h[t][e] = gelu(z[t][e]);
+            stage_t(H, h, col, g);
+            __syncthreads();
+#pragma unroll 4
+            for (int i = 0; i < 16; ++i) {
+                const int idx = w + 4 * i, tn = idx >> 3, tk = idx & 7;
+                const f32x4 a = dw_tile(G, H, tn, tk, lane);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    put(prow + offW + (16 * tn + 4 * g + e) * NH + 16 * tk + r, first, a[e]);
+            }
+            if (threadIdx.x < NH)
+                put(prow + offB + threadIdx.x, first,
+                    ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
+                        bsum[3][threadIdx.x]);
+            // dH = W^T dZ, dZ(prev) = dH * GELU'(z(prev))
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                f32x4 a{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    a = mfma(packed[(frB + t * 4 + q) * 64 + lane], op[q], a);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    dz[t][e] = a[e] * gelu_grad(z[t][e]);
+            }
+            __syncthreads();
+        }
+
+        // ---- layer 1: dW1 = dZ1^T x
+        stage_t(G, dz, col, g);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = sum16(dz[t][e]);
+                if (r == 0)
+                    bsum[w][16 * t + 4 * g + e] = v;
+            }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * g + e;
+            const float v = (k < NIN && s < B) ? x[s * NIN + (k < NIN ? k : 0)] : 0.0f;
+            H[k * BWD_ROW + col] = (uint16_t)bf16_bits(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int tn = w + 4 * i;
+            const f32x4 a = dw_tile(G, H, tn, 0, lane);
+            if (r < NIN) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    put(prow + OFF_W1 + (16 * tn + 4 * g + e) * NIN + r, first, a[e]);
+            }
+        }
+        if (threadIdx.x < NH)
+            put(prow + OFF_B1 + threadIdx.x, first,
+                ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
+                    bsum[3][threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_mlp_reduce(float *__restrict__ grad, const float *__restrict__ part, int rows)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM)
+        return;
+    float acc = 0.0f;
+    for (int w = 0; w < rows; ++w)
+        acc += part[(int64_t)w * NPARAM + i];
+    grad[i] = acc;
+}
+
+__global__ __launch_bounds__(1024) void k_mlp_mse(float *__restrict__ dy, float *__restrict__ loss,
+                                                  const float *__restrict__ yv,
+                                                  const float *__restrict__ tv, int64_t n)
+{
+    __shared__ float red[1024];
+    const float scale = 2.0f / (float)n;
+    float acc = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const float d = yv[i] - tv[i];
+        dy[i] = scale * d;
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int m = 512; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m)
+            red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss)
+        *loss = red[0] / (float)n;
+}
+
+struct AdamF {
+    float lr, b1, omb1, b2, omb2, eps, c1, c2;  // omb = 1 - beta, c = 1 / (1 - beta^t)
+};
+
+__global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
+                           const float *__restrict__ grad, AdamF h)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM)
+        return;
+    const float gi = grad[i];
+    const float mi = h.b1 * m[i] + h.omb1 * gi;
+    const float vi = h.b2 * v[i] + h.omb2 * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    P[i] = P[i] - h.lr * (mi * h.c1) / (sqrtf(vi * h.c2) + h.eps);
+}
+
+struct Box5 {
+    float lo[5], hi[5];
+};
+
+__global__ void k_hull(uint8_t *__restrict__ fb, unsigned long long *__restrict__ counters,
+                       const float *__restrict__ x, int64_t B, Box5 box)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int out = 0;
+    if (b < B) {
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            const float v = x[b * NIN + i];
+            if (!(v >= box.lo[i] && v <= box.hi[i]))
+                out = 1;
+        }
+        fb[b] = (uint8_t)out;
+    }
+    if (counters) {
+        const int c = __syncthreads_count(out);
+        if (threadIdx.x == 0 && c > 0)
+            atomicAdd(counters + SDM_CNT_FALLBACK, (unsigned long long)c);
+    }
+}
+
+struct Std5 {
+    double mean[5], std[5];
+};
+
+__global__ void k_features(float *__restrict__ x, const double *__restrict__ M, int64_t n,
+                           double dt, double kid, Std5 st)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n)
+        return;
+    const double raw[5] = {log(M[c * 3 + 0]), log(M[c * 3 + 1]), log(M[c * 3 + 2]), dt, kid};
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        x[c * NIN + i] = (float)((raw[i] - st.mean[i]) / st.std[i]);
+}
+
+struct Std3 {
+    double mean[3], std[3];
+};
+
+__global__ void k_apply(double *__restrict__ M, const float *__restrict__ yv,
+                        const uint8_t *__restrict__ fb, int64_t n, double dt, Std3 st)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || (fb && fb[c]))
+        return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double tend = (double)yv[c * 3 + k] * st.std[k] + st.mean[k];
+        M[c * 3 + k] = M[c * 3 + k] * (1.0 + dt * tend);
+    }
+}
+
+inline int grid_for(int64_t n, int per)
+{
+    return (int)((n + per - 1) / per);
+}
+
+int check_mlp(const sdm_ctx *ctx, const sdm_mlp *w)
+{
+    if (!ctx || !w || !w->params || !w->packed)
+        return fail(SDM_E_INVALID, "null context or network");
+    if (((uintptr_t)w->packed & 15) != 0)
+        return fail(SDM_E_INVALID, "packed weights must be 16-byte aligned");
+    return SDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdm_mlp_pack(sdm_ctx *ctx, const sdm_mlp *w, hipStream_t stream)
+{
+    if (int rc = check_mlp(ctx, w))
+        return rc;
+    SDM_TRY
+    hipLaunchKernelGGL(k_mlp_pack, dim3(grid_for(FR_N * 256, 256)), dim3(256), 0, stream,
+                       (uint32_t *)w->packed, (const float *)w->params);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_t B,
+                    const sdm_mlp *w, hipStream_t stream)
+{
+    if (int rc = check_mlp(ctx, w))
+        return rc;
+    REQUIRE(B >= 0, "B < 0");
+    if (B == 0)
+        return SDM_OK;
+    REQUIRE(y && x, "null y or x");
+    REQUIRE(B <= ((int64_t)1 << 34), "B too large");
+    SDM_TRY
+    const int64_t tiles = (B + 15) / 16;
+    if (cache) {
+        hipLaunchKernelGGL((k_mlp_forward<1, true>), dim3(grid_for(tiles, 4)), dim3(256), 0,
+                           stream, y, cache, x, B, (const u32x4 *)w->packed, w->params);
+    } else {
+        constexpr int S = 4;
+        hipLaunchKernelGGL((k_mlp_forward<S, false>), dim3(grid_for(tiles, 4 * S)), dim3(256), 0,
+                           stream, y, cache, x, B, (const u32x4 *)w->packed, w->params);
+    }
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_backward(sdm_ctx *ctx, float *grad, const float *dy, const float *x,
+                     const float *cache, int64_t B, const sdm_mlp *w, hipStream_t stream)
+{
+    if (int rc = check_mlp(ctx, w))
+        return rc;
+    REQUIRE(grad, "grad is NULL");
+    REQUIRE(B >= 0, "B < 0");
+    REQUIRE(B == 0 || (dy && x && cache), "null dy, x or cache");
+    REQUIRE(B <= ((int64_t)1 << 34), "B too large");
+    SDM_TRY
+    const int64_t chunks = (B + BWD_CHUNK - 1) / BWD_CHUNK;
+    const int rows = (int)(chunks < PART_ROWS_MAX ? chunks : PART_ROWS_MAX);
+    if (rows > ctx->mlp_part_rows) {
+        SDM_HIP(hipDeviceSynchronize());
+        if (ctx->mlp_part)
+            SDM_HIP(hipFree(ctx->mlp_part));
+        ctx->mlp_part = nullptr;
+        ctx->mlp_part_rows = 0;
+        SDM_HIP(hipMalloc(&ctx->mlp_part, (size_t)rows * NPARAM * sizeof(float)));
+        ctx->mlp_part_rows = rows;
+    }
+    if (rows > 0)
+        hipLaunchKernelGGL(k_mlp_backward, dim3(rows), dim3(256), 0, stream, ctx->mlp_part, dy,
+                           x, cache, B, (const u32x4 *)w->packed, chunks);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(NPARAM, 256)), dim3(256), 0, stream, grad,
+                       ctx->mlp_part, rows);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_mse(sdm_ctx *ctx, float *dy, float *loss, const float *y, const float *t, int64_t B,
+                hipStream_t stream)
+{
+    REQUIRE(ctx, "ctx is NULL");
+    REQUIRE(B > 0, "B must be positive");
+    REQUIRE(dy && y && t, "null dy, y or t");
+    SDM_TRY
+    hipLaunchKernelGGL(k_mlp_mse, dim3(1), dim3(1024), 0, stream, dy, loss, y, t, B * NOUT);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_adam(sdm_ctx *ctx, const sdm_mlp *w, const sdm_mlp_opt *opt, const float *grad,
+                 const sdm_adam_hp *hp, hipStream_t stream)
+{
+    if (int rc = check_mlp(ctx, w))
+        return rc;
+    REQUIRE(opt && opt->m && opt->v && grad && hp, "null optimiser state, grad or hp");
+    REQUIRE(hp->t >= 1, "Adam step t must be >= 1");
+    REQUIRE(hp->beta1 >= 0 && hp->beta1 < 1 && hp->beta2 >= 0 && hp->beta2 < 1,
+            "betas out of [0, 1)");
+    SDM_TRY
+    AdamF h;
+    h.lr = (float)hp->lr;
+    h.b1 = (float)hp->beta1;
+    h.omb1 = (float)(1.0 - hp->beta1);
+    h.b2 = (float)hp->beta2;
+    h.omb2 = (float)(1.0 - hp->beta2);
+    h.eps = (float)hp->eps;
+    h.c1 = (float)(1.0 / (1.0 - pow(hp->beta1, (double)hp->t)));
+    h.c2 = (float)(1.0 / (1.0 - pow(hp->beta2, (double)hp->t)));
+    hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(NPARAM, 256)), dim3(256), 0, stream, w->params,
+                       opt->m, opt->v, grad, h);
+    hipLaunchKernelGGL(k_mlp_pack, dim3(grid_for(FR_N * 256, 256)), dim3(256), 0, stream,
+                       (uint32_t *)w->packed, (const float *)w->params);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_hull_check(sdm_ctx *ctx, uint8_t *fallback, uint64_t *counters_dev, const float *x,
+                   int64_t B, const float *lo, const float *hi, hipStream_t stream)
+{
+    REQUIRE(ctx && lo && hi, "null ctx, lo or hi");
+    REQUIRE(B >= 0, "B < 0");
+    if (B == 0)
+        return SDM_OK;
+    REQUIRE(fallback && x, "null fallback or x");
+    SDM_TRY
+    Box5 box;
+    for (int i = 0; i < NIN; ++i) {
+        box.lo[i] = lo[i];
+        box.hi[i] = hi[i];
+    }
+    hipLaunchKernelGGL(k_hull, dim3(grid_for(B, 256)), dim3(256), 0, stream, fallback,
+                       (unsigned long long *)counters_dev, x, B, box);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_features(sdm_ctx *ctx, float *x, const double *M, int64_t n, double dt,
+                     int32_t kernel_id, const float *mean, const float *std, hipStream_t stream)
+{
+    REQUIRE(ctx && mean && std, "null ctx, mean or std");
+    REQUIRE(n >= 0, "n < 0");
+    if (n == 0)
+        return SDM_OK;
+    REQUIRE(x && M, "null x or M");
+    SDM_TRY
+    Std5 st;
+    for (int i = 0; i < NIN; ++i) {
+        st.mean[i] = mean[i];
+        st.std[i] = std[i];
+    }
+    hipLaunchKernelGGL(k_features, dim3(grid_for(n, 256)), dim3(256), 0, stream, x, M, n, dt,
+                       (double)kernel_id, st);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_mlp_apply(sdm_ctx *ctx, double *M, const float *y, const uint8_t *fallback, int64_t n,
+                  double dt, const float *mean, const float *std, hipStream_t stream)
+{
+    REQUIRE(ctx && mean && std, "null ctx, mean or std");
+    REQUIRE(n >= 0, "n < 0");
+    if (n == 0)
+        return SDM_OK;
+    REQUIRE(M && y, "null M or y");
+    SDM_TRY
+    Std3 st;
+    for (int i = 0; i < 3; ++i) {
+        st.mean[i] = mean[i];
+        st.std[i] = std[i];
+    }
+    hipLaunchKernelGGL(k_apply, dim3(grid_for(n, 256)), dim3(256), 0, stream, M, y, fallback, n,
+                       dt, st);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+}  // extern "C"

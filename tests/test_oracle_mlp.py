@@ -211,3 +211,12 @@ def test_features_and_tendencies():
     assert np.allclose(x, [[0.0, 2.0, 0.0, 0.5, 1.0]], rtol=0, atol=1e-6)
     assert np.allclose(mlp.tendencies([[2.0, 4.0, 8.0]], [[1.0, 4.0, 16.0]], 0.5),
                        [[-1.0, 0.0, 2.0]])
+
+
+def test_apply_hand_case():
+    M = np.array([[1.0, 2.0, 4.0], [8.0, 8.0, 8.0]])
+    y = np.array([[1.0, 0.0, -1.0], [5.0, 5.0, 5.0]], np.float32)
+    out = mlp.apply(M, y, np.array([0, 1], np.uint8), 0.5, [0.0, 1.0, 0.0], [2.0, 1.0, 0.5])
+    # T = (2, 1, -0.5); M (1 + 0.5 T) = (2, 3, 3); the second cell falls back
+    assert np.array_equal(out, [[2.0, 3.0, 3.0], [8.0, 8.0, 8.0]])
+    assert np.array_equal(mlp.apply(M, y, None, 0.0, [0, 0, 0], [1, 1, 1]), M)
