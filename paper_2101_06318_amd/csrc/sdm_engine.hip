@@ -3,7 +3,7 @@
 // Step 1 of the paper (Sec. 2.2, Sec. 3.2) orders each cell's live SDs by a
 // random key (the GPU strategy the paper describes: a sort with random
 // keys) and pairs neighbours; Steps 2-3 evaluate eq. (3), gamma and
-// eqs. (4)-(6) per pair.  Three kernels:
+// eqs. (4)-(6) per pair.  Five kernels:
 //
 //  k_tile    one workgroup per tile of T SD slots (coalesced reads of xi and
 //            v): Step 0 liveness (xi > 0), Philox shuffle key, bucket =
@@ -12,16 +12,19 @@
 //            LDS staging, with the tile's per-bucket offsets.  No global
 //            atomics except one per tile (live total) and one per (tile, big
 //            cell).
+//  k_colsum, k_bscan
+//            bucket totals (column sums of the tile offsets) and their
+//            exclusive scan: the global start rank of every bucket, hence of
+//            every group and cell.
 //  k_group   one workgroup per group of consecutive buckets: gathers the
-//            group's run from every tile, obtains its rank offset by a
-//            decoupled look-back over the groups, sorts in LDS (counting
-//            sort by the next key bits, then exact ranks by (key, s) in each
+//            group's run from every tile, sorts in LDS (counting sort by the
+//            next key bits, then exact ranks by (key, s) in each
 //            sub-bucket), writes idx, and evaluates the pairs: probability,
 //            gamma (one Philox block per two slots) and the collision update,
-//            written back only for pairs that collide.  A pair straddling
-//            two groups leaves a seam record.
+//            written back only for pairs that collide.  Groups are
+//            independent; a pair straddling two groups leaves a seam record.
 //  k_finish  the straddling pairs, the live count, and the per-launch
-//            bookkeeping (tickets, epoch).
+//            bookkeeping.
 //
 // A group with more records than its LDS capacity is sorted in global
 // memory by a bitonic network instead (exact, only slower; for i.i.d. keys
@@ -48,20 +51,6 @@ constexpr double BUCKET_TARGET = 4096.0;
 constexpr double GROUP_TARGET = 4096.0;
 constexpr uint32_t NO_BUCKET = 0xFFFFu;
 
-// look-back status word: kind (2 bits) | epoch (30 bits) | value (32 bits)
-constexpr uint64_t ST_AGG = 1ull, ST_PRE = 2ull;
-__device__ __forceinline__ uint64_t st_pack(uint64_t kind, uint32_t epoch, uint32_t v)
-{
-    return (kind << 62) | ((uint64_t)(epoch & 0x3FFFFFFFu) << 32) | v;
-}
-__device__ __forceinline__ uint64_t load64_agent(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store64_agent(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint32_t load32_agent(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -119,10 +108,7 @@ struct GroupArgs {
     const uint64_t *rec_xi;
     const double *rec_v;
     const int32_t *cell_id;
-    const uint32_t *cell_tot;
-    uint32_t *n_acc;
-    uint64_t *gstat;
-    uint64_t *cstat;
+    const uint32_t *bucket_start;
     uint32_t *cell_start;
     uint64_t *sk;
     uint32_t *ss;
@@ -279,6 +265,57 @@ __device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_
     if (threadIdx.x == 0)
         arr[n] = total;
     __syncthreads();
+}
+
+// ---------------------------------------------------------------- k_scan
+// Global start rank of every bucket.  k_colsum: bucket totals, the column
+// sums of the tiles' bucket offsets (one wave per bucket); k_bscan: their
+// exclusive scan in one workgroup.  Two launches instead of a last-block
+// handshake: no device-scope fence right after the tile kernel's writes.
+struct ScanArgs {
+    const uint16_t *tile_off;
+    int32_t n_tiles;
+    int32_t B;
+    uint32_t *bucket_tot;    // [B]
+    uint32_t *bucket_start;  // [B+1]
+};
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
+{
+    constexpr int W = THREADS / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int b = blockIdx.x * W + wid;
+    if (b >= a.B)
+        return;
+    const int64_t Bp = a.B + 1;
+    uint32_t sum = 0;
+    for (int t = lane; t < a.n_tiles; t += 64)
+        sum += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        sum += __shfl_xor(sum, o, 64);
+    if (lane == 0)
+        a.bucket_tot[b] = sum;
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_bscan(ScanArgs a)
+{
+    __shared__ uint32_t red[THREADS / 64 + 1];
+    const int per = (a.B + THREADS - 1) / THREADS;
+    const int i0 = min(a.B, (int)threadIdx.x * per), i1 = min(a.B, i0 + per);
+    uint32_t sum = 0;
+    for (int i = i0; i < i1; ++i)
+        sum += a.bucket_tot[i];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<THREADS>(sum, red, &total);
+    for (int i = i0; i < i1; ++i) {
+        a.bucket_start[i] = run;
+        run += a.bucket_tot[i];
+    }
+    if (threadIdx.x == 0)
+        a.bucket_start[a.B] = total;
 }
 
 // ---------------------------------------------------------------- k_tile
@@ -739,59 +776,6 @@ __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int
     return b - (uint32_t)b0;
 }
 
-// Block-wide decoupled look-back: exclusive prefix of the group totals of
-// groups [0, g), THREADS predecessors per round (one per thread).  The
-// nearest inclusive prefix in the window ends the walk once every group
-// after it in the window has published its aggregate.
-template <int THREADS>
-__device__ uint32_t look_back(const GroupArgs &a, int g, uint32_t epoch, uint32_t *lb,
-                              uint32_t *red)
-{
-    const int tid = threadIdx.x;
-    const uint32_t ep = epoch & 0x3FFFFFFFu;
-    uint64_t prefix = 0;
-    int j0 = g - 1;
-    while (g > 0) {
-        const int j = j0 - tid;
-        const uint64_t w = j >= 0 ? load64_agent(&a.gstat[j]) : st_pack(ST_PRE, epoch, 0);
-        const uint64_t kind = w >> 62;
-        const bool ready = kind != 0 && (((uint32_t)(w >> 32) & 0x3FFFFFFFu) == ep);
-        if (tid == 0) {
-            lb[0] = THREADS;  // nearest inclusive prefix
-            lb[1] = 0;        // someone before it is not ready
-        }
-        __syncthreads();
-        if (ready && kind == ST_PRE)
-            atomicMin(&lb[0], (uint32_t)tid);
-        __syncthreads();
-        const uint32_t p = lb[0];
-        if (!ready && (uint32_t)tid <= p)
-            lb[1] = 1;
-        __syncthreads();
-        const bool retry = lb[1] != 0;
-        if (!retry) {
-            uint64_t v = ((uint32_t)tid <= p && ready) ? (uint64_t)(uint32_t)w : 0ull;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-                v += __shfl_xor(v, o, 64);
-            if ((tid & 63) == 0) {
-                red[2 * (tid >> 6)] = (uint32_t)v;
-                red[2 * (tid >> 6) + 1] = (uint32_t)(v >> 32);
-            }
-        }
-        __syncthreads();
-        if (retry)
-            continue;
-        for (int wv = 0; wv < THREADS / 64; ++wv)
-            prefix += (uint64_t)red[2 * wv] | ((uint64_t)red[2 * wv + 1] << 32);
-        __syncthreads();
-        if (p < (uint32_t)THREADS)
-            break;
-        j0 -= THREADS;
-    }
-    return (uint32_t)prefix;
-}
-
 // --------------------------------------------------------------- k_group
 template <int THREADS, int EPT>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
@@ -800,7 +784,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t run_pre[MAX_TILES + 1];
     __shared__ uint16_t run_lo[MAX_TILES];
     __shared__ uint32_t t_off[MAXB + 1];
-    __shared__ uint32_t t_cnt[MAXB];
     __shared__ uint32_t t_subbase[MAXB + 1];
     __shared__ uint32_t t_shift[MAXB];
     __shared__ uint32_t t_mask[MAXB];
@@ -809,32 +792,31 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ PairCtx t_pc[MAXB];
     // sub-bucket histogram during the sort, opener list afterwards
     __shared__ uint32_t sub_hist[(NSUB + 1) > (CAP / 2 + 1) ? (NSUB + 1) : (CAP / 2 + 1)];
-    __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans, look-back and flush_stats
+    __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and flush_stats
     __shared__ uint32_t s_misc[8];
     __shared__ __align__(16) unsigned char pool[CAP * 20];
 
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        s_misc[0] = atomicAdd(&a.n_acc[1], 1u);  // logical group id
-        s_misc[1] = load32_agent(&a.n_acc[2]);   // epoch
-        s_misc[2] = 0;
-    }
-    __syncthreads();
-    const int g = (int)s_misc[0];
-    const uint32_t epoch = s_misc[1];
+    const int g = blockIdx.x;
     const int b0 = a.group_first[g], b1 = a.group_first[g + 1];
     const int nb = b1 - b0;
     const int nt = a.n_tiles;
     const int64_t Bp = a.B + 1;
     const bool fused = a.mode == MODE_FUSED;
+    const uint32_t rank0 = a.bucket_start[b0];
+    const uint32_t tot = a.bucket_start[b1] - rank0;
+    if (tid == 0)
+        s_misc[2] = 0;
 
-    // 1. this group's run in every tile; bucket tables; big-cell sizes
+    // 1. this group's run in every tile; bucket and cell tables
     for (int t = tid; t < nt; t += THREADS) {
         const uint32_t lo = a.tile_off[t * Bp + b0];
         const uint32_t hi = a.tile_off[t * Bp + b1];
         run_lo[t] = (uint16_t)lo;
         run_pre[t] = hi - lo;
     }
+    for (int i = tid; i <= nb; i += THREADS)
+        t_off[i] = a.bucket_start[b0 + i] - rank0;
     for (int i = tid; i < nb; i += THREADS) {
         const int b = b0 + i;
         const int c = a.bucket_cell[b];
@@ -843,38 +825,25 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         t_shift[i] = (uint32_t)(53 - h - u);
         t_mask[i] = (1u << u) - 1u;
         t_subbase[i] = 1u << u;
-        t_n[i] = a.cell_big[c] ? load32_agent(&a.cell_tot[c]) : 0u;
-        t_cnt[i] = 0;
+        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
+        const uint32_t cs = a.bucket_start[first];
+        const uint32_t n_c = a.bucket_start[last] - cs;
+        t_cs[i] = cs;
+        t_n[i] = n_c;
+        if (b == first)
+            a.cell_start[c] = cs;
+        if (fused)
+            t_pc[i] = pair_ctx(a, c, cs, n_c);
     }
     __syncthreads();
-    if (nb > 1) {
-        // per-bucket counts of this group, summed over the tiles
-        for (int idx = tid; idx < nb * nt; idx += THREADS) {
-            const int i = idx / nt, t = idx - i * nt;
-            const int b = b0 + i;
-            const uint32_t d =
-                (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
-            if (d)
-                atomicAdd(&t_cnt[i], d);
-        }
-        __syncthreads();
-    }
     lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, nt, red);
-    const uint32_t tot = run_pre[nt];
     if (tid == 0) {
-        // publish this group's total at once: the sort below needs no rank
-        store64_agent(&a.gstat[g], st_pack(g == 0 ? ST_PRE : ST_AGG, epoch, tot));
-        if (nb == 1)
-            t_cnt[0] = tot;
-        uint32_t off = 0, sub = 0;
+        uint32_t sub = 0;
         for (int i = 0; i < nb; ++i) {
-            t_off[i] = off;
-            off += t_cnt[i];
             const uint32_t ns = t_subbase[i];
             t_subbase[i] = sub;
             sub += ns;
         }
-        t_off[nb] = off;
         t_subbase[nb] = sub;
     }
     const uint32_t cap_here =
@@ -896,6 +865,12 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         uint16_t *SB1 = reinterpret_cast<uint16_t *>(pool + 14 * CAP);
         uint16_t *FP = reinterpret_cast<uint16_t *>(pool + 16 * CAP);
         const uint32_t nsub = t_subbase[nb];
+        // tile of each gathered record (aliases FP, written after the sort)
+        uint16_t *tmap = reinterpret_cast<uint16_t *>(pool + 16 * CAP);
+        for (int t = tid; t < nt; t += THREADS)
+            for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
+                tmap[li] = (uint16_t)t;
+        __syncthreads();
         uint64_t key[EPT], xv[EPT];
         double vv[EPT];
         uint32_t sid[EPT], sbk[EPT], lrk[EPT];
@@ -903,7 +878,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
             if (li < tot) {
-                const int t = upper_index(run_pre, nt, li);
+                const int t = tmap[li];
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
                 key[e] = a.rec_key[pos];
                 sid[e] = a.rec_s[pos];
@@ -973,44 +948,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
     }
 
-    // 3. rank offset of the group (all predecessors have long published
-    //    their totals), cell starts, per-cell constants
-    const uint32_t rank0 = look_back<THREADS>(a, g, epoch, &s_misc[4], red);
-    if (tid == 0) {
-        if (g > 0)
-            store64_agent(&a.gstat[g], st_pack(ST_PRE, epoch, rank0 + tot));
-        const int c0 = a.bucket_cell[b0];
-        if (a.cell_bucket_base[c0] < b0) {
-            // start rank of a big cell that began in an earlier group
-            uint64_t w;
-            do {
-                w = load64_agent(&a.cstat[c0]);
-            } while ((uint32_t)(w >> 32) != epoch + 1u);
-            s_misc[3] = (uint32_t)w;
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < nb; i += THREADS) {
-        const int b = b0 + i;
-        const int c = a.bucket_cell[b];
-        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
-        uint32_t cs;
-        if (first >= b0) {
-            cs = rank0 + t_off[first - b0];
-            if (b == first) {
-                a.cell_start[c] = cs;
-                if (a.cell_big[c])
-                    store64_agent(&a.cstat[c], ((uint64_t)(epoch + 1u) << 32) | cs);
-            }
-        } else {
-            cs = s_misc[3];
-        }
-        const uint32_t n_c = a.cell_big[c] ? t_n[i] : t_off[last - b0] - t_off[first - b0];
-        t_cs[i] = cs;
-        t_n[i] = n_c;
-        if (fused)
-            t_pc[i] = pair_ctx(a, c, cs, n_c);
-    }
+    // the sorted records (LDS path) are read by other threads below
     __syncthreads();
     const GroupTabs T{t_off, t_cs, t_n, t_pc};
 
@@ -1109,8 +1047,6 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
             *a.n_live_out = (int64_t)n;
             a.cell_start[a.n_cell] = n;
             a.n_acc[0] = 0;
-            a.n_acc[1] = 0;
-            a.n_acc[2] = (a.n_acc[2] + 1u) & 0x3FFFFFFFu;
         }
     }
     if (a.step_advance) {
@@ -1274,8 +1210,8 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         }
         p->cell_tot = (uint32_t *)dalloc(p, 4ull * C);
         p->n_acc = (uint32_t *)dalloc(p, 64);
-        p->gstat = (uint64_t *)dalloc(p, 8ull * p->G);
-        p->cstat = (uint64_t *)dalloc(p, 8ull * C);
+        p->bucket_tot = (uint32_t *)dalloc(p, 4ull * B);
+        p->bucket_start = (uint32_t *)dalloc(p, 4ull * (B + 1));
         p->cell_start_ws = (uint32_t *)dalloc(p, 4ull * (C + 1));
         p->n_live_ws = (int64_t *)dalloc(p, 8);
         p->sk = (uint64_t *)dalloc(p, 16ull * n_items + 64);
@@ -1287,8 +1223,6 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->group_tot = (uint32_t *)dalloc(p, 4ull * p->G);
         SDM_HIP(hipMemset(p->cell_tot, 0, 4ull * C));
         SDM_HIP(hipMemset(p->n_acc, 0, 64));
-        SDM_HIP(hipMemset(p->gstat, 0, 8ull * p->G));
-        SDM_HIP(hipMemset(p->cstat, 0, 8ull * C));
         SDM_HIP(hipMemset(p->seam_state, 0, 4ull * p->G));
         SDM_HIP(hipMemset(p->group_tot, 0, 4ull * p->G));
         SDM_HIP(hipDeviceSynchronize());
@@ -1439,6 +1373,19 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
             launch_tile<4, false>(p->n_tiles, lds, stream, ta);
     }
     SDM_HIP(hipGetLastError());
+    {
+        ScanArgs sa{};
+        sa.tile_off = p->tile_off;
+        sa.n_tiles = p->n_tiles;
+        sa.B = p->B;
+        sa.bucket_tot = p->bucket_tot;
+        sa.bucket_start = p->bucket_start;
+        constexpr int ST = 256;
+        hipLaunchKernelGGL((k_colsum<ST>), dim3((p->B + ST / 64 - 1) / (ST / 64)), dim3(ST), 0,
+                           stream, sa);
+        hipLaunchKernelGGL((k_bscan<1024>), dim3(1), dim3(1024), 0, stream, sa);
+        SDM_HIP(hipGetLastError());
+    }
 
     GroupArgs ga{};
     ga.mode = p->mode;
@@ -1458,10 +1405,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.rec_xi = p->rec_xi;
     ga.rec_v = p->rec_v;
     ga.cell_id = in.cell_id;
-    ga.cell_tot = p->cell_tot;
-    ga.n_acc = p->n_acc;
-    ga.gstat = p->gstat;
-    ga.cstat = p->cstat;
+    ga.bucket_start = p->bucket_start;
     ga.cell_start = cell_start;
     ga.sk = p->sk;
     ga.ss = p->ss;

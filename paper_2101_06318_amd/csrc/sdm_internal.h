@@ -110,9 +110,9 @@ struct Plan {
     uint64_t *rec_xi = nullptr;           // (fused)
     double *rec_v = nullptr;              // (fused)
     uint32_t *cell_tot = nullptr;         // [C] (big cells; zero between launches)
-    uint32_t *n_acc = nullptr;            // [0] live total [1] group ticket [2] epoch [3] seam ticket
-    uint64_t *gstat = nullptr;            // [G] look-back status
-    uint64_t *cstat = nullptr;            // [C] start rank of big cells
+    uint32_t *n_acc = nullptr;            // [0] live total [1] unused [2] unused [3] finish ticket
+    uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
+    uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
     uint32_t *cell_start_ws = nullptr;    // [C+1]
     int64_t *n_live_ws = nullptr;         // [1]
     uint64_t *sk = nullptr;               // [2 n_items + 8] global-sort scratch
