@@ -43,7 +43,7 @@ constexpr int TILE_THREADS = 1024;
 constexpr int GROUP_THREADS = 1024;
 constexpr int GROUP_EPT = 6;
 constexpr int MAXB = 64;             // buckets per group
-constexpr int NSUB = 1024;           // sub-buckets per group
+constexpr int NSUB = 4096;           // sub-buckets per group
 constexpr int MAX_TILES = 1024;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
@@ -139,6 +139,7 @@ struct GroupArgs {
     SeamRec *seam_close;
     uint32_t *seam_state;
     uint32_t *group_tot;
+    uint32_t *group_stats;  // [G][5] collision statistics per group
 };
 
 struct FinishArgs {
@@ -149,6 +150,7 @@ struct FinishArgs {
     const SeamRec *seam_close;
     const uint32_t *seam_state;
     const uint32_t *group_tot;
+    const uint32_t *group_stats;
     uint64_t *xi;
     double *attr;
     int32_t n_attr;
@@ -724,8 +726,29 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
                 finish_pair(a, T.pc[bv[u]], qv[u], pv[u], phi[u], sa[u], xa[u], sb_[u], xb[u],
                             st);
     }
-    if (a.counters)
-        flush_stats<THREADS>(st, a.counters, red);
+    if (a.counters) {
+        // per-group sums, added up by the finish kernel (no contended atomics)
+        constexpr int W = THREADS / 64;
+        uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                v[i] += __shfl_xor(v[i], o, 64);
+        }
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                red[i * W + (tid >> 6)] = v[i];
+        }
+        __syncthreads();
+        if (tid < 5) {
+            uint32_t sum = 0;
+            for (int w = 0; w < W; ++w)
+                sum += red[tid * W + w];
+            a.group_stats[g * 5 + tid] = sum;
+        }
+    }
     if (tid == 0) {
         a.seam_state[g] = s_misc[2];
         a.group_tot[g] = tot;
@@ -1022,6 +1045,14 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
     const int g = blockIdx.x * THREADS + threadIdx.x;
     const uint32_t step = step_of(a.step, a.step_dev);
     Stats st{0, 0, 0, 0, 0};
+    if (a.mode == MODE_FUSED && a.counters && g < a.G) {
+        const uint32_t *gs = a.group_stats + (int64_t)g * 5;
+        st.pairs = gs[0];
+        st.coll = gs[1];
+        st.capped = gs[2];
+        st.zeroed = gs[3];
+        st.ge2 = gs[4];
+    }
     if (a.mode == MODE_FUSED && g < a.G && (a.seam_state[g] & 1u)) {
         const SeamRec op = a.seam_open[g];
         int g2 = g + 1;
@@ -1137,7 +1168,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             cell_bb[c] = B;
             const double e = m / std::ldexp(1.0, h);
             int u = 0;
-            while (e / std::ldexp(1.0, u + 1) >= 4.0 && u < 10)
+            while (e / std::ldexp(1.0, u + 1) >= 1.0 && u < 12)
                 ++u;
             if (u > 53 - h)
                 u = 53 - h;
@@ -1221,6 +1252,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->seam_close = (SeamRec *)dalloc(p, sizeof(SeamRec) * p->G);
         p->seam_state = (uint32_t *)dalloc(p, 4ull * p->G);
         p->group_tot = (uint32_t *)dalloc(p, 4ull * p->G);
+        p->group_stats = (uint32_t *)dalloc(p, 20ull * p->G);
         SDM_HIP(hipMemset(p->cell_tot, 0, 4ull * C));
         SDM_HIP(hipMemset(p->n_acc, 0, 64));
         SDM_HIP(hipMemset(p->seam_state, 0, 4ull * p->G));
@@ -1436,6 +1468,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.seam_close = p->seam_close;
     ga.seam_state = p->seam_state;
     ga.group_tot = p->group_tot;
+    ga.group_stats = p->group_stats;
     mark(1);
     hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT>), dim3(p->G), dim3(GROUP_THREADS), 0,
                        stream, ga);
@@ -1449,6 +1482,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     fa.seam_close = p->seam_close;
     fa.seam_state = p->seam_state;
     fa.group_tot = p->group_tot;
+    fa.group_stats = p->group_stats;
     fa.xi = in.xi;
     fa.attr = in.attr;
     fa.n_attr = in.n_attr;

@@ -122,6 +122,7 @@ struct Plan {
     SeamRec *seam_close = nullptr;        // [G]
     uint32_t *seam_state = nullptr;       // [G]
     uint32_t *group_tot = nullptr;        // [G]
+    uint32_t *group_stats = nullptr;      // [G][5] collision statistics
     std::vector<void *> allocs;
 };
 
