@@ -1,23 +1,36 @@
-"""Throughput of the fused SDM coagulation step on one MI355X.
+"""Throughput of the SDM coagulation step (and of its moment surrogate) on one
+MI355X.  One JSON line per run.
 
-Workload: the paper's Golovin box (arXiv:2101.06318, Sec. 4: dV = 1e6 m^3,
-N0 = 2^23 m^-3, exponential volumes with mean (4 pi/3)(30.531 um)^3,
-b = 1500 1/s, dt = 1 s), scaled to 2^22 super-droplets, synthetic, seed 2.
-A step is one whole timestep (Steps 0-3: removal, shuffle, pairing, pair
-probability, gamma, collision update) through the C ABI (sdm_step, three
-kernels).  W warm-up steps run first; then exactly K steps are timed on
-one stream, bracketed by synchronisation, with HIP events recorded by the
-library before and after each of its kernels on that stream (per-kernel
-durations for the roofline).  The same K steps are then also captured in a
-HIP graph and replayed once; that time is reported as graph_ms_per_step.
+Workloads (--workload, default box):
 
-Prints one JSON line (metric, value, ..., roofline, cpu_baseline).
+  box        the paper's Golovin box (arXiv:2101.06318, Sec. 4: dV = 1e6 m^3,
+             N0 = 2^23 m^-3, exponential volumes with mean
+             (4 pi/3)(30.531 um)^3, b = 1500 1/s, dt = 1 s), scaled to
+             2^22 super-droplets (--log2-n-sd), synthetic, seed 2.  A step is
+             one whole timestep (Steps 0-3 of the workflow figure) through the
+             C ABI (sdm_step).
+  grid       128 x 128 cells, Poisson(64) SDs per cell clipped to [2, 512],
+             wet and dry volume attributes, gravitational kernel, random cell
+             reassignment before every step (sdm_reassign + sdm_step).
+  ensemble   1024 independent boxes of 2^8..2^16 SDs (log-uniform), Golovin
+             and gravitational kernels alternating, advanced together
+             (sdm_batch_step) with the autotuned schedule.
+  surrogate  the moment surrogate's step for the 16384 cells of the grid
+             (features, hull test, bf16 MFMA forward, moment update), beside
+             one SDM step of the same grid (cell-steps/s of both).
+
+W warm-up steps run first; then exactly K steps are timed on one stream,
+bracketed by synchronisation; the library records HIP events between its
+kernels on that stream, which give the per-kernel durations for the roofline
+of the dominant kernel.  The same K steps are also captured in a HIP graph
+and replayed once (graph_ms_per_step).  The oracle (plain C, one host
+thread) is timed on a bounded sample of the same workload (cpu_baseline).
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,7 +41,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-METRIC = "SDM pair-steps/s at n_sd=2^22"
+BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_PER_SAMPLE = 67584.0      # 2 (5*128 + 128*128*2 + 128*3)
 
 
 def source_hash():
@@ -36,22 +50,6 @@ def source_hash():
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2101_06318_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
-
-
-def algorithmic_bytes(n_sd, f_coll):
-    """Algorithmic HBM bytes of one step, split per kernel.
-
-    Per pair-step (two SDs): xi (8 B) and volume (8 B) read for each SD,
-    the Index written (4 B) and read (4 B) for each SD, and the two SDs'
-    xi and volume written back when the pair collides (32 B * f_coll):
-    48 + 32 f_coll bytes.  The scatter kernel is charged the reads (40 B per
-    pair), the group kernel the Index write and the write-back
-    (8 + 32 f_coll B per pair)."""
-    pairs = n_sd // 2
-    return dict(step=pairs * (48.0 + 32.0 * f_coll),
-                k_scatter=pairs * 40.0,
-                k_group=pairs * (8.0 + 32.0 * f_coll),
-                k_seams=0.0)
 
 
 def traffic_record(kernel, workload):
@@ -81,6 +79,14 @@ class HipEvent:
             raise RuntimeError("hipEventCreate failed")
         self.cuda_event = h.value
 
+    def record(self, stream):
+        import ctypes
+        fn = self._lib.hipEventRecord
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        fn.restype = ctypes.c_int
+        if fn(ctypes.c_void_p(self.cuda_event), ctypes.c_void_p(stream.cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
     def elapsed_ms(self, other):
         import ctypes
         f = ctypes.c_float(0.0)
@@ -100,52 +106,86 @@ class HipEvent:
         fn(ctypes.c_void_p(self.cuda_event))
 
 
-def cpu_baseline(w, n_steps):
-    import numpy as np
-
-    import oracle
-    n = w["n_sd"]
-    st = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
-    t0 = time.perf_counter()
-    for t in range(n_steps):
-        st = oracle.step(st["xi"], st["attr"], None, 1, w["dv"], st["idx"], st["n_live"],
-                         dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"], seed=2,
-                         run=0, step=t)
-    dt = time.perf_counter() - t0
-    return dict(value=(n // 2) * n_steps / dt, unit="pair-steps/s", cores=1, kind="oracle",
-                sample="%d steps of the 2^%d-SD Golovin box (seed 2) from its initial state, "
-                       "oracle (plain C, one thread, qsort-based shuffle)"
-                       % (n_steps, n.bit_length() - 1),
-                seconds=round(dt, 3))
+# Step kernels between the library's four event marks.
+INTERVALS = ("k_tile+k_scan", "k_group", "k_finish")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--log2-n-sd", type=int, default=22)
-    ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="also run one plain 256 MiB device-to-device copy (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the SDM step of one run on one "
-              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def algorithmic_bytes(pairs, f_coll, per_pair_read, per_pair_write_idx, per_pair_coll):
+    """Algorithmic HBM bytes of one step, split per kernel: per pair, the
+    state of two SDs read and the Index read (charged to the tile kernel),
+    the Index written and the write-back of a colliding pair (charged to
+    the group kernel, times the collision fraction)."""
+    return {"step": pairs * (per_pair_read + per_pair_write_idx + per_pair_coll * f_coll),
+            "k_tile+k_scan": pairs * per_pair_read,
+            "k_group": pairs * (per_pair_write_idx + per_pair_coll * f_coll),
+            "k_finish": 0.0}
 
-    import numpy as np
-    import torch
 
-    import paper_2101_06318_amd as sdm
-    from paper_2101_06318_amd import workloads
+def timed_steps(sdm, torch, run_step, K, lib):
+    """K steps on one stream with the library's event marks; returns the total
+    wall time (ms) and the mean duration of each marked interval."""
+    ev = [[HipEvent(lib) for _ in range(4)] for _ in range(K)]
+    stream = torch.cuda.Stream()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for t in range(K):
+            run_step(t, stream, ev[t])
+        end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    per = {k: [] for k in INTERVALS}
+    for t in range(K):
+        for i, k in enumerate(INTERVALS):
+            per[k].append(ev[t][i].elapsed_ms(ev[t][i + 1]))
+    for row in ev:
+        for e in row:
+            e.destroy()
+    return total_ms, {k: sum(v) / len(v) for k, v in per.items()}, stream
 
-    if not os.path.exists(sdm.LIB_PATH):
-        from paper_2101_06318_amd import build
-        build.build()
-    torch.cuda.set_device(0)
+
+def graph_ms(torch, run_step, K, stream):
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            with torch.cuda.graph(g, stream=stream):
+                for t in range(K):
+                    run_step(t, stream, None)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        gs = torch.cuda.Event(enable_timing=True)
+        ge = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            gs.record(stream)
+            g.replay()
+            ge.record(stream)
+        torch.cuda.synchronize()
+        del g
+        return gs.elapsed_time(ge) / K
+    except Exception as e:  # reported, not fatal
+        print("bench: graph replay not measured (%s)" % e, file=sys.stderr, flush=True)
+        return None
+
+
+def roofline(ab, kernel_ms, workload):
+    dom = max(kernel_ms, key=kernel_ms.get)
+    achieved = ab[dom] / (kernel_ms[dom] / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_record(dom, workload)}
+
+
+def base_line(metric, value, unit, K, W, ms, dtype, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": K,
+            "warmup": W, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+# ---------------------------------------------------------------- workloads
+def bench_box(args, sdm, torch, np, workloads):
     n_sd = 1 << args.log2_n_sd
     w = workloads.box(n_sd, seed=2)
     ctx = sdm.Context(n_sd, 1, 1)
@@ -154,9 +194,311 @@ def main():
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     r = sdm.rng(2, 0, 0, step_dev=step_dev)
     kw = dict(dv=w["dv"][0], step_advance=step_dev)
-    print("bench: n_sd=2^%d warmup=%d steps=%d" % (args.log2_n_sd, args.warmup, args.steps),
-          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.step(st, w["dt"], k, r, **kw)
+    torch.cuda.synchronize()
+    c0 = st.counters.cpu().numpy().copy()
 
+    def run_step(t, stream, ev):
+        ctx.step(st, w["dt"], k, r, stream=stream, events=ev, **kw)
+
+    K = args.steps
+    total_ms, kms, stream = timed_steps(sdm, torch, run_step, K, sdm.lib())
+    c1 = st.counters.cpu().numpy()
+    gms = None if args.eager else graph_ms(torch, run_step, K, stream)
+    pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) // K
+    f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
+    assert ctx.read_errors() == 0
+    # per pair: xi and v of two SDs (32 B) and their Index entries (8 B)
+    # read, Index written (8 B), xi and v of both written back on a
+    # collision (32 B): 48 + 32 f_coll
+    ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
+    workload = "golovin_box_2_%d" % args.log2_n_sd
+    out = base_line("SDM pair-steps/s at n_sd=2^%d" % args.log2_n_sd,
+                    (n_sd // 2) * K / (total_ms / 1e3), "pair-steps/s", K, args.warmup,
+                    total_ms / K, "f64",
+                    {"workload": workload, "n_sd": n_sd, "cells": 1, "kernel": "golovin",
+                     "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 2,
+                     "timing": "eager, one stream, HIP events per kernel",
+                     "n_live": int(st.n_live.item()), "collision_fraction": f_coll})
+    out["roofline"] = roofline(ab, kms, workload)
+    out["kernel_ms"] = kms
+    out["graph_ms_per_step"] = gms
+    step_gbs = ab["step"] / (total_ms / K / 1e3) / 1e9
+    out["step_roofline"] = {"bound": "hbm", "bytes_per_step": ab["step"], "achieved": step_gbs,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": step_gbs / HBM_PEAK_GBS}
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n = n_sd
+        s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
+        t0 = time.perf_counter()
+        for t in range(args.cpu_steps):
+            s = oracle.step(s["xi"], s["attr"], None, 1, w["dv"], s["idx"], s["n_live"],
+                            dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
+                            seed=2, run=0, step=t)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": (n // 2) * args.cpu_steps / dt, "unit": "pair-steps/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": "%d steps of the 2^%d-SD Golovin box (seed 2) from its initial state, "
+                      "oracle (plain C, one thread, qsort-based shuffle)"
+                      % (args.cpu_steps, args.log2_n_sd)}
+    ctx.close()
+    return out
+
+
+def bench_grid(args, sdm, torch, np, workloads):
+    w = workloads.grid(seed=3)
+    n_sd, n_cell = w["n_sd"], w["n_cell"]
+    ctx = sdm.Context(n_sd, n_cell, 2)
+    st = sdm.State(w["xi"], w["attr"], w["cell_id"], n_cell)
+    dv = torch.as_tensor(np.asarray(w["dv"], np.float64)).cuda()
+    k = sdm.kernel(w["kernel_id"], w["kparams"])
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    r = sdm.rng(3, 0, 0, step_dev=step_dev)
+    reass_ms = []
+
+    def run_step(t, stream, ev):
+        ctx.reassign(st.cell_id, n_sd, n_cell, r, stream=stream)
+        ctx.step(st, w["dt"], k, r, stream=stream, events=ev, dv_per_cell=dv,
+                 step_advance=step_dev)
+
+    for t in range(args.warmup):
+        run_step(t, None, None)
+    torch.cuda.synchronize()
+    c0 = st.counters.cpu().numpy().copy()
+    K = args.steps
+    total_ms, kms, stream = timed_steps(sdm, torch, run_step, K, sdm.lib())
+    c1 = st.counters.cpu().numpy()
+    gms = None if args.eager else graph_ms(torch, run_step, K, stream)
+    pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
+    f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
+    assert ctx.read_errors() == 0
+    # per pair: xi, two attributes and the cell id of two SDs (56 B) and
+    # their Index entries (8 B) read, Index written (8 B), xi and both
+    # attributes of two SDs written back on a collision (48 B): 72 + 48 f_coll
+    ab = algorithmic_bytes(pairs, f_coll, 64.0, 8.0, 48.0)
+    workload = "grid_128x128"
+    out = base_line("SDM pair-steps/s on the 128x128 grid", pairs * K / (total_ms / 1e3),
+                    "pair-steps/s", K, args.warmup, total_ms / K, "f64",
+                    {"workload": workload, "n_sd": n_sd, "cells": n_cell, "kernel": "geometric",
+                     "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 3,
+                     "reassignment": "every step, inside the timed region",
+                     "pairs_per_step": pairs, "collision_fraction": f_coll})
+    out["cell_steps_per_s"] = n_cell * K / (total_ms / 1e3)
+    out["roofline"] = roofline(ab, kms, workload)
+    out["kernel_ms"] = kms
+    out["graph_ms_per_step"] = gms
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
+        steps = max(1, args.cpu_steps // 2)
+        t0 = time.perf_counter()
+        npairs = 0
+        for t in range(steps):
+            cid = oracle.reassign(n_sd, n_cell, 3, t)
+            s = oracle.step(s["xi"], s["attr"], cid, n_cell, w["dv"], s["idx"], s["n_live"],
+                            dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"], seed=3,
+                            run=0, step=t)
+            npairs += int(s["counters"][oracle.CNT_PAIRS])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "%d reassignment + step passes of the full grid, "
+                                         "oracle (plain C, one thread)" % steps}
+    ctx.close()
+    return out
+
+
+def bench_ensemble(args, sdm, torch, np, workloads):
+    ens = workloads.ensemble(seed=4, n_runs=1024)
+    xi, attr, segs = workloads.ensemble_layout(ens)
+    st = sdm.State(xi, attr, None, len(segs))
+    scratch = sdm.State(xi, attr, None, len(segs))
+    ctx = sdm.Context(st.n_sd, len(segs), 1)
+    b = sdm.Batch(ctx, segs)
+    chosen = b.autotune(scratch, ens["dt"], sdm.rng(4, 0, 0), steps=3)
+    del scratch
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    r = sdm.rng(4, 0, 0, step_dev=step_dev)
+
+    def run_step(t, stream, ev):
+        b.step(st, ens["dt"], r, stream=stream, events=ev, step_advance=step_dev)
+
+    for t in range(args.warmup):
+        run_step(t, None, None)
+    torch.cuda.synchronize()
+    c0 = st.counters.cpu().numpy().copy()
+    K = args.steps
+    total_ms, kms, stream = timed_steps(sdm, torch, run_step, K, sdm.lib())
+    c1 = st.counters.cpu().numpy()
+    gms = None if args.eager else graph_ms(torch, run_step, K, stream)
+    pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
+    f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
+    assert ctx.read_errors() == 0
+    ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
+    workload = "ensemble_1024"
+    out = base_line("SDM pair-steps/s, 1024-run batched ensemble", pairs * K / (total_ms / 1e3),
+                    "pair-steps/s", K, args.warmup, total_ms / K, "f64",
+                    {"workload": workload, "runs": len(segs), "n_sd": int(sum(s[1] for s in segs)),
+                     "kernels": "golovin (even runs), geometric (odd runs)", "dt_s": ens["dt"],
+                     "seed": 4, "schedule": chosen, "pairs_per_step": pairs,
+                     "collision_fraction": f_coll})
+    out["roofline"] = roofline(ab, kms, workload)
+    out["kernel_ms"] = kms
+    out["graph_ms_per_step"] = gms
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        npairs = 0
+        members = ens["runs"][:128]
+        for m in members:
+            s = oracle.step(m["xi"], m["attr"], None, 1, [m["dv"]],
+                            np.arange(m["n_sd"], dtype=np.uint32), m["n_sd"], dt=ens["dt"],
+                            kernel_id=m["kernel_id"], kparams=m["kparams"], seed=4,
+                            run=m["run"], step=0)
+            npairs += int(s["counters"][oracle.CNT_PAIRS])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "one step of the first 128 of the 1024 runs, "
+                                         "oracle (plain C, one thread)"}
+    b.close()
+    ctx.close()
+    return out
+
+
+def bench_surrogate(args, sdm, torch, np, workloads):
+    """Surrogate step for every cell of the grid vs one SDM step of the grid
+    (static cells), both on the GPU; random-init weights (the arithmetic per
+    step does not depend on the weights)."""
+    w = workloads.grid(seed=3)
+    n_sd, n_cell = w["n_sd"], w["n_cell"]
+    ctx = sdm.Context(n_sd, n_cell, 2)
+    st = sdm.State(w["xi"], w["attr"], w["cell_id"], n_cell)
+    dv = torch.as_tensor(np.asarray(w["dv"], np.float64)).cuda()
+    k = sdm.kernel(w["kernel_id"], w["kparams"])
+    ctx.step(st, w["dt"], k, sdm.rng(3, 0, 0), dv_per_cell=dv)
+    M = torch.zeros((n_cell, 3), dtype=torch.float64, device="cuda")
+    ctx.moments(M, st.xi, st.attr[0], st.idx, st.cell_start, n_cell, dv_per_cell=dv)
+    torch.cuda.synchronize()
+    lm = torch.log(M).cpu().numpy()
+    mean = np.concatenate([lm.mean(0), [1.0, 1.0]]).astype(np.float32)
+    std = np.concatenate([lm.std(0) + 1e-6, [1.0, 1.0]]).astype(np.float32)
+    net = sdm.Mlp(ctx, workloads.mlp_init(7))
+    x = torch.zeros((n_cell, 5), dtype=torch.float32, device="cuda")
+    y = torch.zeros((n_cell, 3), dtype=torch.float32, device="cuda")
+    fb = torch.zeros(n_cell, dtype=torch.uint8, device="cuda")
+    lo, hi = [-8.0] * 5, [8.0] * 5
+    tm, ts = [0.0, 0.0, 0.0], [1e-6, 1e-9, 1e-6]
+    lib = sdm.lib()
+    e_fwd = [HipEvent(lib) for _ in range(2 * args.steps)]
+
+    def sur_step(t, stream, ev):
+        ctx.mlp_features(x, M, w["dt"], w["kernel_id"], mean, std, stream=stream)
+        ctx.hull_check(fb, x, lo, hi, stream=stream)
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.mlp_forward(y, x, net, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.mlp_apply(M, y, w["dt"], tm, ts, fallback=fb, stream=stream)
+
+    for t in range(args.warmup):
+        sur_step(t, None, None)
+    K = args.steps
+    stream = torch.cuda.Stream()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        s0.record(stream)
+        for t in range(K):
+            sur_step(t, stream, e_fwd[2 * t:2 * t + 2])
+        s1.record(stream)
+    torch.cuda.synchronize()
+    sur_ms = s0.elapsed_time(s1)
+    fwd_ms = sum(e_fwd[2 * t].elapsed_ms(e_fwd[2 * t + 1]) for t in range(K)) / K
+    for e in e_fwd:
+        e.destroy()
+    gms = None if args.eager else graph_ms(torch, sur_step, K, stream)
+
+    # the particle method on the same cells (no reassignment)
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    r = sdm.rng(3, 0, 1, step_dev=step_dev)
+
+    def sdm_step(t, stream, ev):
+        ctx.step(st, w["dt"], k, r, stream=stream, events=ev, dv_per_cell=dv,
+                 step_advance=step_dev)
+
+    for t in range(args.warmup):
+        sdm_step(t, None, None)
+    sdm_ms, _, _ = timed_steps(sdm, torch, sdm_step, K, lib)
+    flop = MLP_FLOP_PER_SAMPLE * n_cell
+    achieved = flop / (fwd_ms / 1e3) / 1e12
+    out = base_line("surrogate cell-steps/s on the 128x128 grid", n_cell * K / (sur_ms / 1e3),
+                    "cell-steps/s", K, args.warmup, sur_ms / K, "bf16",
+                    {"workload": "surrogate_grid_128x128", "cells": n_cell,
+                     "network": "5-128-128-128-3 GELU", "dt_s": w["dt"], "seed": 3,
+                     "step": "features + hull test + forward + moment update"})
+    out["sdm_cell_steps_per_s"] = n_cell * K / (sdm_ms / 1e3)
+    out["speedup_vs_sdm"] = out["value"] / out["sdm_cell_steps_per_s"]
+    out["roofline"] = {"bound": "mfma", "kernel": "k_mlp_forward", "achieved": achieved,
+                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None}
+    out["kernel_ms"] = {"k_mlp_forward": fwd_ms}
+    out["graph_ms_per_step"] = gms
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        from oracle import mlp
+        xh = x.cpu().numpy()
+        th = workloads.mlp_init(7)
+        net_o = mlp.Net("bf16")
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            net_o.forward(th, xh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_cell * reps / dt, "unit": "cell-steps/s",
+                               "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "%d bf16-emulated forward passes over the 16384 cells "
+                                         "(numpy)" % reps}
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="box", choices=["box", "grid", "ensemble", "surrogate"])
+    ap.add_argument("--log2-n-sd", type=int, default=22)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the SDM step on one MI355X); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_06318_amd as sdm
+    from paper_2101_06318_amd import workloads
+
+    sdm.lib()  # raises if the HIP library is not built
+    torch.cuda.set_device(0)
+    print("bench: workload=%s warmup=%d steps=%d" % (args.workload, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
     if args.calib_copy:
         # A copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
         # the counters of the SDM kernels to bytes.
@@ -166,110 +508,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        ctx.step(st, w["dt"], k, r, **kw)
-    torch.cuda.synchronize()
-    coll0 = int(st.counters.cpu().numpy()[sdm.CNT_COLLISIONS])
-    pairs0 = int(st.counters.cpu().numpy()[sdm.CNT_PAIRS])
-
-    K = args.steps
-    L = sdm.lib()
-    ev = [[HipEvent(L) for _ in range(4)] for _ in range(K)]
-    stream = torch.cuda.Stream()
-
-    # Timed region: exactly K steps on one stream; the library records HIP
-    # events before/after each of its three kernels on that stream.
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        start.record(stream)
-        for t in range(K):
-            ctx.step(st, w["dt"], k, r, stream=stream, events=ev[t], **kw)
-        end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
-    per = {"k_scatter": [], "k_group": [], "k_seams": []}
-    for t in range(K):
-        per["k_scatter"].append(ev[t][0].elapsed_ms(ev[t][1]))
-        per["k_group"].append(ev[t][1].elapsed_ms(ev[t][2]))
-        per["k_seams"].append(ev[t][2].elapsed_ms(ev[t][3]))
-    avg_ms = {kname: float(np.mean(v)) for kname, v in per.items()}
-
-    cnt = st.counters.cpu().numpy()
-    graph_ms = None
-    if not args.eager:
-        # Same K steps captured once in a HIP graph and replayed (reported
-        # beside the timed region; the step index advances on the device).
-        try:
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.stream(stream):
-                with torch.cuda.graph(g, stream=stream):
-                    for t in range(K):
-                        ctx.step(st, w["dt"], k, r, stream=stream, **kw)
-            torch.cuda.synchronize()
-            g.replay()
-            torch.cuda.synchronize()
-            gs = torch.cuda.Event(enable_timing=True)
-            ge = torch.cuda.Event(enable_timing=True)
-            with torch.cuda.stream(stream):
-                gs.record(stream)
-                g.replay()
-                ge.record(stream)
-            torch.cuda.synchronize()
-            graph_ms = gs.elapsed_time(ge) / K
-            del g
-        except Exception as e:
-            print("bench: graph replay not measured (%s)" % e, file=sys.stderr, flush=True)
-    pairs = int(cnt[sdm.CNT_PAIRS]) - pairs0
-    f_coll = (int(cnt[sdm.CNT_COLLISIONS]) - coll0) / max(pairs, 1)
-    n_live = int(st.n_live.item())
-    assert ctx.read_errors() == 0
-    pair_steps = (n_sd // 2) * K
-    value = pair_steps / (total_ms / 1e3)
-    ab = algorithmic_bytes(n_sd, f_coll)
-    dom = max(avg_ms, key=avg_ms.get)
-    achieved = ab[dom] / (avg_ms[dom] / 1e3) / 1e9
-    workload = "golovin_box_2_%d" % args.log2_n_sd
-    traffic = traffic_record(dom, workload)
-    step_gbs = ab["step"] / (total_ms / K / 1e3) / 1e9
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pair-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": total_ms / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": workload, "n_sd": n_sd, "cells": 1, "kernel": "golovin",
-                   "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]),
-                   "seed": 2, "timing": "eager, one stream, HIP events per kernel",
-                   "n_live": n_live,
-                   "collision_fraction": f_coll},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "kernel_ms": avg_ms,
-        "graph_ms_per_step": graph_ms,
-        "step_roofline": {"bound": "hbm", "bytes_per_step": ab["step"], "achieved": step_gbs,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": step_gbs / HBM_PEAK_GBS},
-    }
-    if not args.no_cpu_baseline:
-        print("bench: timing the oracle on the host (%d steps)" % args.cpu_steps,
-              file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
-    else:
-        out["cpu_baseline"] = None
-    for row in ev:
-        for e in row:
-            e.destroy()
-    ctx.close()
+    fn = {"box": bench_box, "grid": bench_grid, "ensemble": bench_ensemble,
+          "surrogate": bench_surrogate}[args.workload]
+    out = fn(args, sdm, torch, np, workloads)
     print(json.dumps(out), flush=True)
 
 

@@ -46,6 +46,7 @@ static_assert(3 * 8 * 64 * 4 == 16 * SDM_MLP_CACHE_FLOATS_PER_ROW, "cache tile s
 constexpr int BWD_CHUNK = 64;      // samples per backward workgroup pass
 constexpr int BWD_ROW = 72;        // LDS row stride (bf16): 64 samples + 8 pad
 constexpr int PART_ROWS_MAX = 128; // backward workgroups (partial-sum rows)
+constexpr int FWD_GRID_MAX = 512;  // forward workgroups (two per CU)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -176,32 +177,12 @@ __device__ inline void hidden_layer(const u32x4 *__restrict__ frags, int layer,
     }
 }
 
-// Forward pass.  Workgroup: 4 waves; wave w takes S consecutive 16-sample
-// tiles.  The forward fragments (76 KiB) and biases are staged in LDS.
 template <int S, bool TRAIN>
-__global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
-                                                     float *__restrict__ cache,
-                                                     const float *__restrict__ x, int64_t B,
-                                                     const u32x4 *__restrict__ packed,
-                                                     const float *__restrict__ P)
+__device__ inline void forward_tiles(float *__restrict__ y, float *__restrict__ cache,
+                                     const float *__restrict__ x, int64_t B,
+                                     const u32x4 *__restrict__ sw, const float *__restrict__ sb,
+                                     int64_t tile0, int64_t n_tiles, int lane, int r, int g)
 {
-    __shared__ u32x4 sw[FWD_FRAGS * 64];
-    __shared__ float sb[3 * NH + 4];
-    for (int i = threadIdx.x; i < FWD_FRAGS * 64; i += 256)
-        sw[i] = packed[i];
-    for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 256)
-        sb[i] = P[i < NH ? OFF_B1 + i
-                  : i < 2 * NH ? OFF_B2 + (i - NH)
-                  : i < 3 * NH ? OFF_B3 + (i - 2 * NH)
-                               : OFF_B4 + (i - 3 * NH)];
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-    const int64_t n_tiles = (B + 15) / 16;
-    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + w) * S;
-    if (tile0 >= n_tiles)
-        return;
-
     u32x4 ha[S][4], hb[S][4];
     // layer 1: the K x N operand is x itself (features 8g..8g+7 of sample r)
     u32x4 bx[S];
@@ -251,6 +232,36 @@ __global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
         }
     }
 }
+
+// Forward pass.  Workgroup: 4 waves; each wave takes S consecutive
+// 16-sample tiles at a time, striding over the batch (persistent grid), so
+// the forward fragments (76 KiB) and biases are staged in LDS once per
+// workgroup.
+template <int S, bool TRAIN>
+__global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
+                                                     float *__restrict__ cache,
+                                                     const float *__restrict__ x, int64_t B,
+                                                     const u32x4 *__restrict__ packed,
+                                                     const float *__restrict__ P)
+{
+    __shared__ u32x4 sw[FWD_FRAGS * 64];
+    __shared__ float sb[3 * NH + 4];
+    for (int i = threadIdx.x; i < FWD_FRAGS * 64; i += 256)
+        sw[i] = packed[i];
+    for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 256)
+        sb[i] = P[i < NH ? OFF_B1 + i
+                  : i < 2 * NH ? OFF_B2 + (i - NH)
+                  : i < 3 * NH ? OFF_B3 + (i - 2 * NH)
+                               : OFF_B4 + (i - 3 * NH)];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    const int64_t n_tiles = (B + 15) / 16;
+    const int64_t stride = (int64_t)gridDim.x * 4 * S;
+    for (int64_t tile0 = ((int64_t)blockIdx.x * 4 + w) * S; tile0 < n_tiles; tile0 += stride)
+        forward_tiles<S, TRAIN>(y, cache, x, B, sw, sb, tile0, n_tiles, lane, r, g);
+}
+
 
 // ---------------------------------------------------------------- backward
 __device__ inline float sum16(float v)
@@ -630,14 +641,19 @@ int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_
     REQUIRE(B <= ((int64_t)1 << 34), "B too large");
     SDM_TRY
     const int64_t tiles = (B + 15) / 16;
-    if (cache) {
-        hipLaunchKernelGGL((k_mlp_forward<1, true>), dim3(grid_for(tiles, 4)), dim3(256), 0,
-                           stream, y, cache, x, B, (const u32x4 *)w->packed, w->params);
-    } else {
-        constexpr int S = 4;
-        hipLaunchKernelGGL((k_mlp_forward<S, false>), dim3(grid_for(tiles, 4 * S)), dim3(256), 0,
-                           stream, y, cache, x, B, (const u32x4 *)w->packed, w->params);
-    }
+    // two tiles per wave pay off only once every workgroup has several
+    const int S = (!cache && tiles > 4 * 4 * FWD_GRID_MAX) ? 2 : 1;
+    const int64_t want = (tiles + 4 * S - 1) / (4 * S);
+    const int grid = (int)(want < FWD_GRID_MAX ? want : FWD_GRID_MAX);
+    if (cache)
+        hipLaunchKernelGGL((k_mlp_forward<1, true>), dim3(grid), dim3(256), 0, stream, y, cache,
+                           x, B, (const u32x4 *)w->packed, w->params);
+    else if (S == 1)
+        hipLaunchKernelGGL((k_mlp_forward<1, false>), dim3(grid), dim3(256), 0, stream, y,
+                           cache, x, B, (const u32x4 *)w->packed, w->params);
+    else
+        hipLaunchKernelGGL((k_mlp_forward<2, false>), dim3(grid), dim3(256), 0, stream, y,
+                           cache, x, B, (const u32x4 *)w->packed, w->params);
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }

@@ -105,6 +105,15 @@ def test_step_grid_geometric_with_reassignment(sdm, nx):
     ctx.close()
 
 
+def test_full_size_grid_128x128_with_reassignment(sdm):
+    """The 128 x 128 grid at full size (about 1.05e6 SDs, 16384 cells),
+    reassigned before every step as in the benchmark, element by element."""
+    w = workloads.grid(seed=3)
+    ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    _run_pair(sdm, ctx, w, 2, seed=3, reassign=True)
+    ctx.close()
+
+
 def test_step_grid_static_cells(sdm):
     w = workloads.grid(seed=5, nx=64, ny=64, mean_per_cell=20)
     ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
