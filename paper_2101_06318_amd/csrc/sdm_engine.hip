@@ -40,15 +40,16 @@
 namespace sdm {
 
 constexpr int TILE_THREADS = 1024;
-constexpr int GROUP_THREADS = 1024;
-constexpr int GROUP_EPT = 6;
+constexpr int TILE_EPT = 16;      // SD slots per tile thread
+constexpr int GROUP_THREADS = 512;
+constexpr int GROUP_EPT = 8;
 constexpr int MAXB = 64;             // buckets per group
 constexpr int NSUB = 4096;           // sub-buckets per group
-constexpr int MAX_TILES = 1024;      // tiles per launch
+constexpr int MAX_TILES = 2048;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
-constexpr double BUCKET_TARGET = 4096.0;
-constexpr double GROUP_TARGET = 4096.0;
+constexpr double BUCKET_TARGET = 1024.0;
+constexpr double GROUP_TARGET = 3200.0;
 constexpr uint32_t NO_BUCKET = 0xFFFFu;
 
 __device__ __forceinline__ uint32_t load32_agent(const uint32_t *p)
@@ -81,10 +82,9 @@ struct TileArgs {
     const int32_t *big_cells;
     int32_t n_big;
     uint16_t *tile_off;
-    uint64_t *rec_key;
-    uint32_t *rec_s;
-    uint64_t *rec_xi;
-    double *rec_v;
+    RecK *rec_k;
+    RecX *rec_x;
+    uint32_t chunk;        // records per LDS staging pass
     uint32_t *cell_tot;
     uint32_t *n_acc;
     uint32_t *err;
@@ -102,11 +102,9 @@ struct GroupArgs {
     const int32_t *cell_h;
     const int32_t *cell_bucket_base;
     const uint8_t *cell_big;
-    const uint16_t *tile_off;
-    const uint64_t *rec_key;
-    const uint32_t *rec_s;
-    const uint64_t *rec_xi;
-    const double *rec_v;
+    const uint16_t *tile_offT;  // [B+1][n_tiles]
+    const RecK *rec_k;
+    const RecX *rec_x;
     const int32_t *cell_id;
     const uint32_t *bucket_start;
     uint32_t *cell_start;
@@ -271,11 +269,13 @@ __device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_
 
 // ---------------------------------------------------------------- k_scan
 // Global start rank of every bucket.  k_colsum: bucket totals, the column
-// sums of the tiles' bucket offsets (one wave per bucket); k_bscan: their
+// sums of the tiles' bucket offsets (one wave per bucket), and the offsets
+// transposed to bucket-major order for the groups; k_bscan: their
 // exclusive scan in one workgroup.  Two launches instead of a last-block
 // handshake: no device-scope fence right after the tile kernel's writes.
 struct ScanArgs {
     const uint16_t *tile_off;
+    uint16_t *tile_offT;     // [B+1][n_tiles] transposed copy for the groups
     int32_t n_tiles;
     int32_t B;
     uint32_t *bucket_tot;    // [B]
@@ -288,12 +288,18 @@ __global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
     constexpr int W = THREADS / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int b = blockIdx.x * W + wid;
-    if (b >= a.B)
+    if (b > a.B)
         return;
     const int64_t Bp = a.B + 1;
     uint32_t sum = 0;
-    for (int t = lane; t < a.n_tiles; t += 64)
-        sum += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)a.tile_off[t * Bp + b];
+    for (int t = lane; t < a.n_tiles; t += 64) {
+        const uint16_t lo = a.tile_off[t * Bp + b];
+        a.tile_offT[(int64_t)b * a.n_tiles + t] = lo;
+        if (b < a.B)
+            sum += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)lo;
+    }
+    if (b == a.B)
+        return;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         sum += __shfl_xor(sum, o, 64);
@@ -331,7 +337,6 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
     const int hist_bytes = ((B + 1) * 4 + 15) & ~15;
     uint64_t *stage = reinterpret_cast<uint64_t *>(smem + hist_bytes);
-    uint32_t *stage32 = reinterpret_cast<uint32_t *>(stage);
     const int tid = threadIdx.x;
     for (int i = tid; i <= B; i += THREADS)
         hist[i] = 0;
@@ -342,7 +347,6 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
 
     uint64_t key[EPT];
-    uint64_t xv[EPT];
     uint32_t bk[EPT];  // bucket (low 16 bits) | rank in tile (high 16 bits)
     uint32_t sid[LIST ? EPT : 1];
 
@@ -426,7 +430,6 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         for (int e = 0; e < 2; ++e) {
             const int j = 2 * k + e;
             key[j] = kk[e];
-            xv[j] = x[e];
             if (LIST)
                 sid[j] = s[e];
             bk[j] = NO_BUCKET;
@@ -477,64 +480,79 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         const uint32_t b = bk[j] & 0xFFFFu;
         pos[j] = b == NO_BUCKET ? 0xFFFFFFFFu : hist[b] + (bk[j] >> 16);
     }
-    // staged, coalesced write-out of the tile's records in bucket order
+    // staged, coalesced write-out of the tile's records in bucket order, in
+    // passes of a.chunk 16-B halves: first (key, id), then (xi, v)
     const int64_t rbase = (int64_t)blockIdx.x * T;
+    const uint32_t CH = a.chunk;
+    RecK *stk = reinterpret_cast<RecK *>(stage);
+    for (uint32_t c0 = 0; c0 < total; c0 += CH) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j)
-        if (pos[j] != 0xFFFFFFFFu)
-            stage[pos[j]] = key[j];
-    __syncthreads();
-    for (uint32_t i = tid; i < total; i += THREADS)
-        a.rec_key[rbase + i] = stage[i];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        if (pos[j] != 0xFFFFFFFFu) {
-            uint32_t s;
-            if (LIST)
-                s = sid[j];
-            else
-                s = (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
-            stage32[pos[j]] = s;
+        for (int j = 0; j < EPT; ++j) {
+            if (pos[j] - c0 < CH) {  // (pos = 0xFFFFFFFF never lands in a pass)
+                RecK r;
+                r.key = key[j];
+                r.s = LIST ? sid[j]
+                           : (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
+                r.pad = 0;
+                stk[pos[j] - c0] = r;
+            }
         }
+        __syncthreads();
+        const uint32_t n = min(CH, total - c0);
+        const uint4 *src = reinterpret_cast<const uint4 *>(stk);
+        uint4 *dst = reinterpret_cast<uint4 *>(a.rec_k + rbase + c0);
+        for (uint32_t i = tid; i < n; i += THREADS)
+            dst[i] = src[i];
+        __syncthreads();
     }
-    __syncthreads();
-    for (uint32_t i = tid; i < total; i += THREADS)
-        a.rec_s[rbase + i] = stage32[i];
     if (LIST || a.mode != MODE_FUSED)
         return;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EPT; ++j)
-        if (pos[j] != 0xFFFFFFFFu)
-            stage[pos[j]] = xv[j];
-    __syncthreads();
-    for (uint32_t i = tid; i < total; i += THREADS)
-        a.rec_xi[rbase + i] = stage[i];
-    __syncthreads();
-    const double *vsrc = a.v;
-    double *stagev = reinterpret_cast<double *>(stage);
+    // multiplicities (again) and volumes, read only now that the keys are
+    // dead (registers), as coalesced pairs
+    uint64_t xv[EPT];
+    double vv[EPT];
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
         const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
+        uint64_t x0 = 0, x1 = 0;
         double v0 = 0.0, v1 = 0.0;
         if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
             if (i0 + 1 < n_items) {
-                const double2 vv = *reinterpret_cast<const double2 *>(vsrc + i0);
-                v0 = vv.x;
-                v1 = vv.y;
+                const ulonglong2 x2 = *reinterpret_cast<const ulonglong2 *>(a.xi + i0);
+                const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
+                x0 = x2.x;
+                x1 = x2.y;
+                v0 = v2.x;
+                v1 = v2.y;
             } else {
-                v0 = vsrc[i0];
+                x0 = a.xi[i0];
+                v0 = a.v[i0];
             }
         }
-        if (pos[2 * k] != 0xFFFFFFFFu)
-            stagev[pos[2 * k]] = v0;
-        if (pos[2 * k + 1] != 0xFFFFFFFFu)
-            stagev[pos[2 * k + 1]] = v1;
+        xv[2 * k] = x0;
+        xv[2 * k + 1] = x1;
+        vv[2 * k] = v0;
+        vv[2 * k + 1] = v1;
     }
-    __syncthreads();
-    for (uint32_t i = tid; i < total; i += THREADS)
-        a.rec_v[rbase + i] = stagev[i];
+    RecX *stx = reinterpret_cast<RecX *>(stage);
+    for (uint32_t c0 = 0; c0 < total; c0 += CH) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (pos[j] - c0 < CH) {
+                RecX r;
+                r.xi = xv[j];
+                r.v = vv[j];
+                stx[pos[j] - c0] = r;
+            }
+        }
+        __syncthreads();
+        const uint32_t n = min(CH, total - c0);
+        const uint4 *src = reinterpret_cast<const uint4 *>(stx);
+        uint4 *dst = reinterpret_cast<uint4 *>(a.rec_x + rbase + c0);
+        for (uint32_t i = tid; i < n; i += THREADS)
+            dst[i] = src[i];
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------- pair evaluation
@@ -607,7 +625,35 @@ struct GroupTabs {
     PairCtx *pc;       // [nb] per-cell constants (fused mode)
 };
 
-// Output phase shared by the LDS and the global-memory paths.  Get gives
+// Per-group collision statistics into the group's row (summed by k_finish).
+template <int THREADS>
+__device__ __forceinline__ void store_group_stats(const GroupArgs &a, int g, const Stats &st,
+                                                  uint32_t *red)
+{
+    constexpr int W = THREADS / 64;
+    const int tid = threadIdx.x;
+    uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            v[i] += __shfl_xor(v[i], o, 64);
+    }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            red[i * W + (tid >> 6)] = v[i];
+    }
+    __syncthreads();
+    if (tid < 5) {
+        uint32_t sum = 0;
+        for (int w = 0; w < W; ++w)
+            sum += red[tid * W + w];
+        a.group_stats[g * 5 + tid] = sum;
+    }
+}
+
+// Output phase of the global-memory path.  Get gives
 // s / xi / v at local position f.
 template <int THREADS, class Get>
 __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_t tot,
@@ -726,43 +772,13 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
                 finish_pair(a, T.pc[bv[u]], qv[u], pv[u], phi[u], sa[u], xa[u], sb_[u], xb[u],
                             st);
     }
-    if (a.counters) {
-        // per-group sums, added up by the finish kernel (no contended atomics)
-        constexpr int W = THREADS / 64;
-        uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-                v[i] += __shfl_xor(v[i], o, 64);
-        }
-        if ((tid & 63) == 0) {
-#pragma unroll
-            for (int i = 0; i < 5; ++i)
-                red[i * W + (tid >> 6)] = v[i];
-        }
-        __syncthreads();
-        if (tid < 5) {
-            uint32_t sum = 0;
-            for (int w = 0; w < W; ++w)
-                sum += red[tid * W + w];
-            a.group_stats[g * 5 + tid] = sum;
-        }
-    }
+    if (a.counters)
+        store_group_stats<THREADS>(a, g, st, red);
     if (tid == 0) {
         a.seam_state[g] = s_misc[2];
         a.group_tot[g] = tot;
     }
 }
-
-struct LdsGet {
-    const uint32_t *SF;
-    const uint64_t *XF;
-    const double *VF;
-    __device__ uint32_t s(uint32_t f) const { return SF[f]; }
-    __device__ uint64_t xi(uint32_t f) const { return XF[f]; }
-    __device__ double v(uint32_t f) const { return VF[f]; }
-};
 
 struct GlobalGet {
     const uint32_t *ss;
@@ -804,8 +820,6 @@ template <int THREADS, int EPT>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
-    __shared__ uint32_t run_pre[MAX_TILES + 1];
-    __shared__ uint16_t run_lo[MAX_TILES];
     __shared__ uint32_t t_off[MAXB + 1];
     __shared__ uint32_t t_subbase[MAXB + 1];
     __shared__ uint32_t t_shift[MAXB];
@@ -813,11 +827,17 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t t_cs[MAXB];
     __shared__ uint32_t t_n[MAXB];
     __shared__ PairCtx t_pc[MAXB];
-    // sub-bucket histogram during the sort, opener list afterwards
-    __shared__ uint32_t sub_hist[(NSUB + 1) > (CAP / 2 + 1) ? (NSUB + 1) : (CAP / 2 + 1)];
-    __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and flush_stats
+    __shared__ uint32_t sub_hist[NSUB + 1];
+    __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
-    __shared__ __align__(16) unsigned char pool[CAP * 20];
+    // gather: tile map and the group's run in every tile; sort: keys and
+    // ids by sorted position (12 B per record); afterwards the closing SD of
+    // every pair by pair slot (20 B per two records)
+    __shared__ __align__(16) unsigned char pool[CAP * 12];
+    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 2 * MAX_TILES <= 12 * CAP,
+                  "run tables must fit the sort pool");
+    uint32_t *run_pre = reinterpret_cast<uint32_t *>(pool + 2 * CAP);
+    uint16_t *run_lo = reinterpret_cast<uint16_t *>(pool + 2 * CAP + 4 * (MAX_TILES + 1));
 
     const int tid = threadIdx.x;
     const int g = blockIdx.x;
@@ -833,8 +853,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 
     // 1. this group's run in every tile; bucket and cell tables
     for (int t = tid; t < nt; t += THREADS) {
-        const uint32_t lo = a.tile_off[t * Bp + b0];
-        const uint32_t hi = a.tile_off[t * Bp + b1];
+        const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t];
+        const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t];
         run_lo[t] = (uint16_t)lo;
         run_pre[t] = hi - lo;
     }
@@ -876,41 +896,40 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         sub_hist[i] = 0;
     __syncthreads();
 
-    uint64_t *XF = reinterpret_cast<uint64_t *>(pool);
-    double *VF = reinterpret_cast<double *>(pool + 8 * CAP);
-    uint32_t *SF = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
     if (lds_path) {
-        // 2. gather the records and sort them in LDS: counting sort by
-        //    (bucket, next key bits), then exact ranks by (key, s)
+        // 2. gather the records (every thread keeps its EPT records in
+        //    registers), counting sort by (bucket, next key bits) in LDS,
+        //    then each thread ranks its own records by (key, s) within
+        //    their sub-bucket
         uint64_t *K1 = reinterpret_cast<uint64_t *>(pool);
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
-        uint16_t *O1 = reinterpret_cast<uint16_t *>(pool + 12 * CAP);
-        uint16_t *SB1 = reinterpret_cast<uint16_t *>(pool + 14 * CAP);
-        uint16_t *FP = reinterpret_cast<uint16_t *>(pool + 16 * CAP);
+        uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);  // tile of each gathered slot
         const uint32_t nsub = t_subbase[nb];
-        // tile of each gathered record (aliases FP, written after the sort)
-        uint16_t *tmap = reinterpret_cast<uint16_t *>(pool + 16 * CAP);
         for (int t = tid; t < nt; t += THREADS)
             for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
                 tmap[li] = (uint16_t)t;
         __syncthreads();
         uint64_t key[EPT], xv[EPT];
         double vv[EPT];
-        uint32_t sid[EPT], sbk[EPT], lrk[EPT];
+        uint32_t sid[EPT], sbk[EPT], fp[EPT];
+        uint8_t blk[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
+            key[e] = 0;
+            sid[e] = 0;
+            xv[e] = 0;
+            vv[e] = 0.0;
             if (li < tot) {
                 const int t = tmap[li];
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-                key[e] = a.rec_key[pos];
-                sid[e] = a.rec_s[pos];
+                const RecK rk = a.rec_k[pos];
+                key[e] = rk.key;
+                sid[e] = rk.s;
                 if (fused) {
-                    xv[e] = a.rec_xi[pos];
-                    vv[e] = a.rec_v[pos];
-                } else {
-                    xv[e] = 0;
-                    vv[e] = 0.0;
+                    const RecX rx = a.rec_x[pos];
+                    xv[e] = rx.xi;
+                    vv[e] = rx.v;
                 }
             }
         }
@@ -918,11 +937,14 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
             sbk[e] = 0xFFFFFFFFu;
+            blk[e] = 0;
+            fp[e] = 0;
             if (li < tot) {
                 const uint32_t bl = local_bucket(a, b0, nb, key[e], sid[e]);
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
+                blk[e] = (uint8_t)bl;
                 sbk[e] = t_subbase[bl] + sub;
-                lrk[e] = atomicAdd(&sub_hist[sbk[e]], 1u);
+                fp[e] = atomicAdd(&sub_hist[sbk[e]], 1u);  // rank among equal sub-buckets
             }
         }
         __syncthreads();
@@ -930,57 +952,107 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (sbk[e] != 0xFFFFFFFFu) {
-                const uint32_t pos = sub_hist[sbk[e]] + lrk[e];
+                const uint32_t pos = sub_hist[sbk[e]] + fp[e];
                 K1[pos] = key[e];
                 S1[pos] = sid[e];
-                O1[pos] = (uint16_t)(e * THREADS + tid);
-                SB1[pos] = (uint16_t)sbk[e];
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t pos = (uint32_t)(e * THREADS + tid);
-            if (pos < tot) {
-                const uint64_t k = K1[pos];
-                const uint32_t s = S1[pos];
-                const uint32_t b = SB1[pos];
-                const uint32_t lo = sub_hist[b], hi = sub_hist[b + 1];
-                uint32_t r = 0;
-                for (uint32_t q = lo; q < hi; ++q) {
-                    const uint64_t kq = K1[q];
-                    r += (kq < k) || (kq == k && S1[q] < s);
-                }
-                FP[O1[pos]] = (uint16_t)(lo + r);
-            }
-        }
-        __syncthreads();
-        uint32_t fp[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (sbk[e] != 0xFFFFFFFFu)
-                fp[e] = FP[e * THREADS + tid];
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (sbk[e] != 0xFFFFFFFFu) {
-                XF[fp[e]] = xv[e];
-                VF[fp[e]] = vv[e];
-                SF[fp[e]] = sid[e];
+                const uint32_t lo = sub_hist[sbk[e]], hi = sub_hist[sbk[e] + 1];
+                uint32_t r = 0;
+                for (uint32_t q = lo; q < hi; ++q) {
+                    const uint64_t kq = K1[q];
+                    r += (kq < key[e]) || (kq == key[e] && S1[q] < sid[e]);
+                }
+                fp[e] = lo + r;
             }
         }
-    }
+        __syncthreads();  // keys and ids are dead: the pool now holds pair slots
 
-    // the sorted records (LDS path) are read by other threads below
-    __syncthreads();
-    const GroupTabs T{t_off, t_cs, t_n, t_pc};
+        // 3. idx, closing SDs into their pair slot, seam records
+        uint64_t *CX = reinterpret_cast<uint64_t *>(pool);
+        double *CV = reinterpret_cast<double *>(pool + 4 * CAP);
+        uint32_t *CS = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
+        uint32_t opener = 0;  // bit e: record e opens a pair inside the group
+        uint32_t state = 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            if (sbk[e] == 0xFFFFFFFFu)
+                continue;
+            const uint32_t f = fp[e];
+            const uint32_t r = rank0 + f;
+            a.idx_out[r] = sid[e];
+            if (!fused)
+                continue;
+            const uint32_t bl = blk[e];
+            const uint32_t cs = t_cs[bl];
+            const uint32_t ic = r - cs;
+            const bool op = ((ic & 1u) == 0u) && (ic + 1u < t_n[bl]);
+            const bool cl = (ic & 1u) != 0u;
+            if (op && f + 1 < tot) {
+                opener |= 1u << e;
+            } else if (cl && f > 0) {
+                // the pair (f - 1, f): slot f / 2 (two closers are never adjacent)
+                CX[f >> 1] = xv[e];
+                CV[f >> 1] = vv[e];
+                CS[f >> 1] = sid[e];
+            }
+            if ((op && f + 1 >= tot) || (cl && f == 0)) {
+                SeamRec rec;
+                rec.xi = xv[e];
+                rec.v = vv[e];
+                rec.s = sid[e];
+                rec.rank = r;
+                rec.cell = a.bucket_cell[b0 + bl];
+                rec.cs = cs;
+                rec.n_c = t_n[bl];
+                rec.pad = 0;
+                if (op) {
+                    a.seam_open[g] = rec;
+                    state |= 1u;
+                } else {
+                    a.seam_close[g] = rec;
+                    state |= 2u;
+                }
+            }
+        }
+        if (!fused)
+            return;
+        if (state)
+            atomicOr(&s_misc[2], state);
+        __syncthreads();
 
-    if (lds_path) {
-        LdsGet get{SF, XF, VF};
-        // the opener list reuses the sub-bucket histogram (dead after ranking)
-        group_outputs<THREADS>(a, g, b0, nb, tot, rank0, T, get, red, s_misc, sub_hist);
+        // 4. pairs opened by this thread's records: eq. (3), gamma, eqs. (4)-(6)
+        const uint32_t step = step_of(a.step, a.step_dev);
+        Stats st{0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            if (!((opener >> e) & 1u))
+                continue;
+            const uint32_t f = fp[e];
+            const uint32_t c = (f + 1) >> 1;
+            const uint64_t xb = CX[c];
+            const double vb = CV[c];
+            const uint32_t sb2 = CS[c];
+            const PairCtx pc = t_pc[blk[e]];
+            const uint32_t q = (rank0 + f - pc.slot_base) >> 1;
+            const double p = pair_prob(pc, xv[e], vv[e], xb, vb);
+            const double phi =
+                word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
+            finish_pair(a, pc, q, p, phi, sid[e], xv[e], sb2, xb, st);
+        }
+        if (a.counters)
+            store_group_stats<THREADS>(a, g, st, red);
+        if (tid == 0) {
+            a.seam_state[g] = s_misc[2];
+            a.group_tot[g] = tot;
+        }
         return;
     }
+    const GroupTabs T{t_off, t_cs, t_n, t_pc};
 
     // ---------------------------------------------------- global path
     // The group's records are gathered into scratch at [2 rank0, 2 rank0 + P),
@@ -995,8 +1067,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, nt, li);
         const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-        const uint64_t k = a.rec_key[pos];
-        const uint32_t s = a.rec_s[pos];
+        const uint64_t k = a.rec_k[pos].key;
+        const uint32_t s = a.rec_k[pos].s;
         a.sk[base2 + li] = k;
         a.ss[base2 + li] = s;
         a.sb[base2 + li] = local_bucket(a, b0, nb, k, s);
@@ -1132,14 +1204,20 @@ static int ceil_log2_u64(uint64_t x)
     return b;
 }
 
-static int tile_ept_for(int B)
+// Tile kernel LDS: the bucket histogram plus a staging buffer of at least
+// 1024 records (the records of a tile leave in passes of `chunk`).
+static int tile_hist_bytes(int B)
 {
-    const int hist = ((B + 1) * 4 + 15) & ~15;
-    for (int ept : {16, 8, 4}) {
-        if (hist + TILE_THREADS * ept * 8 <= TILE_LDS_BUDGET)
-            return ept;
-    }
-    return 0;
+    return ((B + 1) * 4 + 15) & ~15;
+}
+
+static uint32_t tile_chunk_for(int B, int tile)
+{
+    const int room = TILE_LDS_BUDGET - tile_hist_bytes(B);
+    uint32_t ch = 1024;
+    while ((int)(2 * ch * sizeof(RecK)) <= room && (int)(2 * ch) <= tile)
+        ch *= 2;
+    return (int)(ch * sizeof(RecK)) <= room ? ch : 0;
 }
 
 static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
@@ -1150,7 +1228,22 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
     try {
         (void)ctx;
         const int32_t C = (int32_t)expected.size();
-        const double target = bucket_target;
+        // the bucket table must fit the tile kernel's LDS histogram: coarser
+        // buckets for plans with many SDs
+        double target = bucket_target;
+        for (;;) {
+            int64_t nbk = 0;
+            for (int32_t c = 0; c < C; ++c) {
+                const double m = std::max(expected[c], 1.0);
+                int h = 0;
+                while (m / std::ldexp(1.0, h) > target && h < 20)
+                    ++h;
+                nbk += (int64_t)1 << h;
+            }
+            if (nbk <= MAX_B || target >= 1e12)
+                break;
+            target *= 2.0;
+        }
         p->mode = mode;
         p->n_items = n_items;
         p->n_cell = C;
@@ -1213,10 +1306,10 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                 big_cells.push_back(c);
             }
         }
-        const int ept = tile_ept_for(B);
-        if (ept == 0)
+        p->tile = TILE_THREADS * TILE_EPT;
+        p->chunk = tile_chunk_for(B, p->tile);
+        if (p->chunk == 0)
             throw HipError{hipErrorInvalidValue, "bucket table exceeds the tile LDS budget"};
-        p->tile = TILE_THREADS * ept;
         p->n_tiles = (int32_t)std::max<int64_t>(1, (n_items + p->tile - 1) / p->tile);
         if (p->n_tiles > MAX_TILES)
             throw HipError{hipErrorInvalidValue, "too many SD slots for one plan"};
@@ -1233,12 +1326,10 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         const bool fused = mode == MODE_FUSED;
         const size_t R = (size_t)p->n_tiles * p->tile;
         p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
-        p->rec_key = (uint64_t *)dalloc(p, 8ull * R);
-        p->rec_s = (uint32_t *)dalloc(p, 4ull * R);
-        if (fused) {
-            p->rec_xi = (uint64_t *)dalloc(p, 8ull * R);
-            p->rec_v = (double *)dalloc(p, 8ull * R);
-        }
+        p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
+        p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
+        if (fused)
+            p->rec_x = (RecX *)dalloc(p, sizeof(RecX) * R);
         p->cell_tot = (uint32_t *)dalloc(p, 4ull * C);
         p->n_acc = (uint32_t *)dalloc(p, 64);
         p->bucket_tot = (uint32_t *)dalloc(p, 4ull * B);
@@ -1284,8 +1375,8 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
 // Schedules the batch autotuner chooses from: (expected SDs per key bucket,
 // expected SDs per group).  Results never depend on the choice.
 static const double kSchedules[][2] = {
-    {4096.0, 4096.0}, {2048.0, 4096.0}, {1024.0, 4096.0},
-    {4096.0, 3072.0}, {2048.0, 2048.0}, {1024.0, 2048.0},
+    {1024.0, 3200.0}, {512.0, 3200.0}, {2048.0, 3200.0},
+    {1024.0, 2400.0}, {512.0, 2400.0}, {2048.0, 2048.0},
 };
 int n_schedules() { return (int)(sizeof(kSchedules) / sizeof(kSchedules[0])); }
 
@@ -1379,42 +1470,30 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.big_cells = p->big_cells;
     ta.n_big = p->n_big;
     ta.tile_off = p->tile_off;
-    ta.rec_key = p->rec_key;
-    ta.rec_s = p->rec_s;
-    ta.rec_xi = p->rec_xi;
-    ta.rec_v = p->rec_v;
+    ta.rec_k = p->rec_k;
+    ta.rec_x = p->rec_x;
+    ta.chunk = p->chunk;
     ta.cell_tot = p->cell_tot;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
-    const int ept = p->tile / TILE_THREADS;
-    const size_t lds = (size_t)(((p->B + 1) * 4 + 15) & ~15) + (size_t)p->tile * 8;
+    const size_t lds = (size_t)tile_hist_bytes(p->B) + (size_t)p->chunk * sizeof(RecK);
     mark(0);
-    if (list) {
-        if (ept == 16)
-            launch_tile<16, true>(p->n_tiles, lds, stream, ta);
-        else if (ept == 8)
-            launch_tile<8, true>(p->n_tiles, lds, stream, ta);
-        else
-            launch_tile<4, true>(p->n_tiles, lds, stream, ta);
-    } else {
-        if (ept == 16)
-            launch_tile<16, false>(p->n_tiles, lds, stream, ta);
-        else if (ept == 8)
-            launch_tile<8, false>(p->n_tiles, lds, stream, ta);
-        else
-            launch_tile<4, false>(p->n_tiles, lds, stream, ta);
-    }
+    if (list)
+        launch_tile<TILE_EPT, true>(p->n_tiles, lds, stream, ta);
+    else
+        launch_tile<TILE_EPT, false>(p->n_tiles, lds, stream, ta);
     SDM_HIP(hipGetLastError());
     {
         ScanArgs sa{};
         sa.tile_off = p->tile_off;
+        sa.tile_offT = p->tile_offT;
         sa.n_tiles = p->n_tiles;
         sa.B = p->B;
         sa.bucket_tot = p->bucket_tot;
         sa.bucket_start = p->bucket_start;
         constexpr int ST = 256;
-        hipLaunchKernelGGL((k_colsum<ST>), dim3((p->B + ST / 64 - 1) / (ST / 64)), dim3(ST), 0,
-                           stream, sa);
+        hipLaunchKernelGGL((k_colsum<ST>), dim3((p->B + 1 + ST / 64 - 1) / (ST / 64)), dim3(ST),
+                           0, stream, sa);
         hipLaunchKernelGGL((k_bscan<1024>), dim3(1), dim3(1024), 0, stream, sa);
         SDM_HIP(hipGetLastError());
     }
@@ -1431,11 +1510,9 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_h = p->cell_h;
     ga.cell_bucket_base = p->cell_bucket_base;
     ga.cell_big = p->cell_big;
-    ga.tile_off = p->tile_off;
-    ga.rec_key = p->rec_key;
-    ga.rec_s = p->rec_s;
-    ga.rec_xi = p->rec_xi;
-    ga.rec_v = p->rec_v;
+    ga.tile_offT = p->tile_offT;
+    ga.rec_k = p->rec_k;
+    ga.rec_x = p->rec_x;
     ga.cell_id = in.cell_id;
     ga.bucket_start = p->bucket_start;
     ga.cell_start = cell_start;

@@ -59,6 +59,18 @@ struct HipError {
 // ------------------------------------------------------------ engine plan
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
+// One SD's record between the tile and group kernels, as two 16-B halves:
+// shuffle key and SD id, multiplicity and volume.
+struct __attribute__((aligned(16))) RecK {
+    uint64_t key;
+    uint32_t s;
+    uint32_t pad;
+};
+struct __attribute__((aligned(16))) RecX {
+    uint64_t xi;
+    double v;
+};
+
 // Pair that straddles two groups: the opener's record, written by the
 // group holding it and completed by the seam kernel.
 struct SeamRec {
@@ -105,10 +117,10 @@ struct Plan {
     KernelDesc *kernels = nullptr;        // [n_kernels]
     // workspace
     uint16_t *tile_off = nullptr;         // [n_tiles][B+1]
-    uint64_t *rec_key = nullptr;          // [n_tiles * tile]
-    uint32_t *rec_s = nullptr;
-    uint64_t *rec_xi = nullptr;           // (fused)
-    double *rec_v = nullptr;              // (fused)
+    uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
+    RecK *rec_k = nullptr;                // [n_tiles * tile] records in tile-local bucket order
+    RecX *rec_x = nullptr;                // [n_tiles * tile] (fused mode)
+    uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     uint32_t *cell_tot = nullptr;         // [C] (big cells; zero between launches)
     uint32_t *n_acc = nullptr;            // [0] live total [1] unused [2] unused [3] finish ticket
     uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
