@@ -307,21 +307,30 @@ __global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
         a.bucket_tot[b] = sum;
 }
 
-template <int THREADS>
+template <int THREADS, int PER>
 __global__ __launch_bounds__(THREADS) void k_bscan(ScanArgs a)
 {
+    __shared__ uint32_t buf[THREADS * PER];  // totals, then starts (coalesced in and out)
     __shared__ uint32_t red[THREADS / 64 + 1];
-    const int per = (a.B + THREADS - 1) / THREADS;
-    const int i0 = min(a.B, (int)threadIdx.x * per), i1 = min(a.B, i0 + per);
+    for (int i = threadIdx.x; i < THREADS * PER; i += THREADS)
+        buf[i] = i < a.B ? a.bucket_tot[i] : 0u;
+    __syncthreads();
+    const int i0 = (int)threadIdx.x * PER;
     uint32_t sum = 0;
-    for (int i = i0; i < i1; ++i)
-        sum += a.bucket_tot[i];
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        sum += buf[i0 + i];
     uint32_t total;
     uint32_t run = block_exclusive_scan<THREADS>(sum, red, &total);
-    for (int i = i0; i < i1; ++i) {
-        a.bucket_start[i] = run;
-        run += a.bucket_tot[i];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t v = buf[i0 + i];
+        buf[i0 + i] = run;
+        run += v;
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.B; i += THREADS)
+        a.bucket_start[i] = buf[i];
     if (threadIdx.x == 0)
         a.bucket_start[a.B] = total;
 }
@@ -1494,7 +1503,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
         constexpr int ST = 256;
         hipLaunchKernelGGL((k_colsum<ST>), dim3((p->B + 1 + ST / 64 - 1) / (ST / 64)), dim3(ST),
                            0, stream, sa);
-        hipLaunchKernelGGL((k_bscan<1024>), dim3(1), dim3(1024), 0, stream, sa);
+        hipLaunchKernelGGL((k_bscan<1024, MAX_B / 1024>), dim3(1), dim3(1024), 0, stream, sa);
         SDM_HIP(hipGetLastError());
     }
 

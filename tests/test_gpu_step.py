@@ -221,3 +221,34 @@ def test_bad_cell_id_is_reported(sdm):
     assert ctx.read_errors() & 1
     assert int(host(st.n_live)[0]) == w["n_sd"] - 1
     ctx.close()
+
+
+def test_checkpoint_resume_equals_uninterrupted(sdm):
+    """The step's state is (xi, attributes, cell ids) plus the step index:
+    copying it to the host after step 3 and resuming in a fresh context
+    gives the uninterrupted trajectory bit for bit."""
+    w = workloads.grid(seed=13, nx=16, ny=16)
+    n_sd, n_cell = w["n_sd"], w["n_cell"]
+    dv = dev(np.asarray(w["dv"], np.float64))
+    k = sdm.kernel(w["kernel_id"], [80.0])
+
+    def run(st, ctx, t0, t1):
+        for t in range(t0, t1):
+            ctx.reassign(st.cell_id, n_sd, n_cell, sdm.rng(21, 0, t))
+            ctx.step(st, w["dt"], k, sdm.rng(21, 0, t), dv_per_cell=dv)
+
+    ctx = sdm.Context(n_sd, n_cell, 2)
+    a = sdm.State(w["xi"], w["attr"], w["cell_id"], n_cell)
+    run(a, ctx, 0, 6)
+    b = sdm.State(w["xi"], w["attr"], w["cell_id"], n_cell)
+    run(b, ctx, 0, 3)
+    _sync()
+    saved = (host(b.xi).copy(), host(b.attr).copy(), host(b.cell_id).copy())
+    ctx.close()
+    ctx2 = sdm.Context(n_sd, n_cell, 2)
+    c = sdm.State(*saved, n_cell)
+    run(c, ctx2, 3, 6)
+    _sync()
+    for name in ("xi", "attr", "idx", "cell_start", "n_live"):
+        assert np.array_equal(host(getattr(a, name)), host(getattr(c, name))), name
+    ctx2.close()
