@@ -82,9 +82,10 @@ struct TileArgs {
     const int32_t *big_cells;
     int32_t n_big;
     uint16_t *tile_off;
-    RecK *rec_k;
-    RecX *rec_x;
-    uint32_t chunk;        // records per LDS staging pass
+    RecK *rec_k;           // list modes: (key, id)
+    uint32_t *rec_s;       // fused mode: id (the key is recomputed from it)
+    RecX *rec_x;           // fused mode: (xi, v)
+    uint32_t chunk;        // 16-B records per LDS staging pass
     uint32_t *cell_tot;
     uint32_t *n_acc;
     uint32_t *err;
@@ -104,6 +105,7 @@ struct GroupArgs {
     const uint8_t *cell_big;
     const uint16_t *tile_offT;  // [B+1][n_tiles]
     const RecK *rec_k;
+    const uint32_t *rec_s;
     const RecX *rec_x;
     const int32_t *cell_id;
     const uint32_t *bucket_start;
@@ -356,6 +358,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
 
     uint64_t key[EPT];
+    uint64_t xv[EPT];
     uint32_t bk[EPT];  // bucket (low 16 bits) | rank in tile (high 16 bits)
     uint32_t sid[LIST ? EPT : 1];
 
@@ -439,6 +442,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         for (int e = 0; e < 2; ++e) {
             const int j = 2 * k + e;
             key[j] = kk[e];
+            xv[j] = x[e];
             if (LIST)
                 sid[j] = s[e];
             bk[j] = NO_BUCKET;
@@ -489,57 +493,65 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         const uint32_t b = bk[j] & 0xFFFFu;
         pos[j] = b == NO_BUCKET ? 0xFFFFFFFFu : hist[b] + (bk[j] >> 16);
     }
-    // staged, coalesced write-out of the tile's records in bucket order, in
-    // passes of a.chunk 16-B halves: first (key, id), then (xi, v)
+    // staged, coalesced write-out of the tile's records in bucket order.
+    // Fused mode: ids (the group kernel recomputes the keys from them), then
+    // (xi, v); list modes: (key, id).  Passes of a.chunk 16-B records.
     const int64_t rbase = (int64_t)blockIdx.x * T;
     const uint32_t CH = a.chunk;
-    RecK *stk = reinterpret_cast<RecK *>(stage);
-    for (uint32_t c0 = 0; c0 < total; c0 += CH) {
+    if (LIST) {  // the list modes (the fused step always runs LIST = false)
+        RecK *stk = reinterpret_cast<RecK *>(stage);
+        for (uint32_t c0 = 0; c0 < total; c0 += CH) {
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (pos[j] - c0 < CH) {  // (pos = 0xFFFFFFFF never lands in a pass)
-                RecK r;
-                r.key = key[j];
-                r.s = LIST ? sid[j]
-                           : (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
-                r.pad = 0;
-                stk[pos[j] - c0] = r;
+            for (int j = 0; j < EPT; ++j) {
+                if (pos[j] - c0 < CH) {  // (pos = 0xFFFFFFFF never lands in a pass)
+                    RecK r;
+                    r.key = key[j];
+                    r.s = LIST ? sid[j]
+                               : (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
+                                            (j & 1));
+                    r.pad = 0;
+                    stk[pos[j] - c0] = r;
+                }
             }
+            __syncthreads();
+            const uint32_t n = min(CH, total - c0);
+            const uint4 *src = reinterpret_cast<const uint4 *>(stk);
+            uint4 *dst = reinterpret_cast<uint4 *>(a.rec_k + rbase + c0);
+            for (uint32_t i = tid; i < n; i += THREADS)
+                dst[i] = src[i];
+            __syncthreads();
         }
+        return;
+    }
+    uint32_t *sts = reinterpret_cast<uint32_t *>(stage);
+    const uint32_t CHS = 4 * CH;  // ids per pass
+    for (uint32_t c0 = 0; c0 < total; c0 += CHS) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            if (pos[j] - c0 < CHS)
+                sts[pos[j] - c0] =
+                    (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
         __syncthreads();
-        const uint32_t n = min(CH, total - c0);
-        const uint4 *src = reinterpret_cast<const uint4 *>(stk);
-        uint4 *dst = reinterpret_cast<uint4 *>(a.rec_k + rbase + c0);
+        const uint32_t n = min(CHS, total - c0);
         for (uint32_t i = tid; i < n; i += THREADS)
-            dst[i] = src[i];
+            a.rec_s[rbase + c0 + i] = sts[i];
         __syncthreads();
     }
-    if (LIST || a.mode != MODE_FUSED)
-        return;
-    // multiplicities (again) and volumes, read only now that the keys are
-    // dead (registers), as coalesced pairs
-    uint64_t xv[EPT];
+    // volumes, read now as coalesced pairs (the keys are dead)
     double vv[EPT];
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
         const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
-        uint64_t x0 = 0, x1 = 0;
         double v0 = 0.0, v1 = 0.0;
         if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
             if (i0 + 1 < n_items) {
-                const ulonglong2 x2 = *reinterpret_cast<const ulonglong2 *>(a.xi + i0);
                 const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
-                x0 = x2.x;
-                x1 = x2.y;
                 v0 = v2.x;
                 v1 = v2.y;
             } else {
-                x0 = a.xi[i0];
                 v0 = a.v[i0];
             }
         }
-        xv[2 * k] = x0;
-        xv[2 * k + 1] = x1;
         vv[2 * k] = v0;
         vv[2 * k + 1] = v1;
     }
@@ -808,6 +820,20 @@ __device__ __forceinline__ bool rec_less(uint32_t ba, uint64_t ka, uint32_t sa,
     return sa < sbb;
 }
 
+// Shuffle key of SD s (fused mode): the same Philox word the tile kernel
+// drew for it, element s - offset of its run.
+__device__ __forceinline__ uint64_t shuffle_key(const GroupArgs &a, uint32_t s, uint32_t step)
+{
+    uint32_t run = a.run;
+    uint64_t e = s;
+    if (a.seg_off) {
+        const int seg = find_seg(a.seg_off, a.n_cell, s);
+        run = (uint32_t)a.seg_run[seg];
+        e = (uint64_t)(s - a.seg_off[seg]);
+    }
+    return philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, e) >> 11;
+}
+
 // Local bucket of a record of this group.
 __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int nb, uint64_t key,
                                                  uint32_t s)
@@ -932,15 +958,24 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             if (li < tot) {
                 const int t = tmap[li];
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-                const RecK rk = a.rec_k[pos];
-                key[e] = rk.key;
-                sid[e] = rk.s;
                 if (fused) {
+                    sid[e] = a.rec_s[pos];
                     const RecX rx = a.rec_x[pos];
                     xv[e] = rx.xi;
                     vv[e] = rx.v;
+                } else {
+                    const RecK rk = a.rec_k[pos];
+                    key[e] = rk.key;
+                    sid[e] = rk.s;
                 }
             }
+        }
+        if (fused) {
+            const uint32_t step = step_of(a.step, a.step_dev);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if ((uint32_t)(e * THREADS + tid) < tot)
+                    key[e] = shuffle_key(a, sid[e], step);
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -1076,8 +1111,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, nt, li);
         const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-        const uint64_t k = a.rec_k[pos].key;
-        const uint32_t s = a.rec_k[pos].s;
+        const uint32_t s = fused ? a.rec_s[pos] : a.rec_k[pos].s;
+        const uint64_t k =
+            fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
         a.sk[base2 + li] = k;
         a.ss[base2 + li] = s;
         a.sb[base2 + li] = local_bucket(a, b0, nb, k, s);
@@ -1336,9 +1372,12 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         const size_t R = (size_t)p->n_tiles * p->tile;
         p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
-        p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
-        if (fused)
+        if (fused) {
+            p->rec_s = (uint32_t *)dalloc(p, 4ull * R);
             p->rec_x = (RecX *)dalloc(p, sizeof(RecX) * R);
+        } else {
+            p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
+        }
         p->cell_tot = (uint32_t *)dalloc(p, 4ull * C);
         p->n_acc = (uint32_t *)dalloc(p, 64);
         p->bucket_tot = (uint32_t *)dalloc(p, 4ull * B);
@@ -1480,6 +1519,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.n_big = p->n_big;
     ta.tile_off = p->tile_off;
     ta.rec_k = p->rec_k;
+    ta.rec_s = p->rec_s;
     ta.rec_x = p->rec_x;
     ta.chunk = p->chunk;
     ta.cell_tot = p->cell_tot;
@@ -1521,6 +1561,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_big = p->cell_big;
     ga.tile_offT = p->tile_offT;
     ga.rec_k = p->rec_k;
+    ga.rec_s = p->rec_s;
     ga.rec_x = p->rec_x;
     ga.cell_id = in.cell_id;
     ga.bucket_start = p->bucket_start;

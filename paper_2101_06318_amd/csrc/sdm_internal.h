@@ -59,8 +59,9 @@ struct HipError {
 // ------------------------------------------------------------ engine plan
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
-// One SD's record between the tile and group kernels, as two 16-B halves:
-// shuffle key and SD id, multiplicity and volume.
+// One SD's record between the tile and group kernels: (shuffle key, id) in
+// the list modes; id and (multiplicity, volume) in the fused step, whose
+// group kernel recomputes the key from the id.
 struct __attribute__((aligned(16))) RecK {
     uint64_t key;
     uint32_t s;
@@ -118,8 +119,10 @@ struct Plan {
     // workspace
     uint16_t *tile_off = nullptr;         // [n_tiles][B+1]
     uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
-    RecK *rec_k = nullptr;                // [n_tiles * tile] records in tile-local bucket order
-    RecX *rec_x = nullptr;                // [n_tiles * tile] (fused mode)
+    // records in tile-local bucket order, [n_tiles * tile]
+    RecK *rec_k = nullptr;                // list modes: (key, id)
+    uint32_t *rec_s = nullptr;            // fused mode: id
+    RecX *rec_x = nullptr;                // fused mode: (xi, v)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     uint32_t *cell_tot = nullptr;         // [C] (big cells; zero between launches)
     uint32_t *n_acc = nullptr;            // [0] live total [1] unused [2] unused [3] finish ticket
