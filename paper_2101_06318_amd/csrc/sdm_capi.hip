@@ -75,10 +75,12 @@ static int check_state(const sdm_ctx *ctx, const sdm_state *st, const sdm_step_p
     REQUIRE(st->n_attr >= 1 && st->n_attr <= ctx->n_attr_max, "n_attr %d out of range",
             st->n_attr);
     REQUIRE(st->attr_stride >= st->n_sd, "attr_stride < n_sd");
-    REQUIRE(st->xi && st->attr && st->idx && st->n_live_dev && st->cell_start,
-            "state pointer is NULL");
-    REQUIRE(st->n_cell == 1 || st->cell_id, "cell_id is NULL with n_cell > 1");
-    REQUIRE(((uintptr_t)st->xi & 15) == 0, "xi must be 16-byte aligned");
+    REQUIRE(st->n_live_dev && st->cell_start, "state pointer is NULL");
+    if (st->n_sd > 0) {  // an empty state may carry null arrays
+        REQUIRE(st->xi && st->attr && st->idx, "state pointer is NULL");
+        REQUIRE(st->n_cell == 1 || st->cell_id, "cell_id is NULL with n_cell > 1");
+        REQUIRE(((uintptr_t)st->xi & 15) == 0, "xi must be 16-byte aligned");
+    }
     REQUIRE(p->dv_per_cell || p->dv > 0, "need dv_per_cell or dv > 0");
     REQUIRE(p->kernel.id >= SDM_KERNEL_GOLOVIN && p->kernel.id <= SDM_KERNEL_MULTIPLICATIVE,
             "unknown kernel id %d", p->kernel.id);

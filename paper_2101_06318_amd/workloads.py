@@ -94,7 +94,7 @@ def ensemble(seed: int = 4, n_runs: int = 1024, log2_min: float = 8.0,
         sub = np.random.Generator(np.random.PCG64(seed * 1_000_003 + r))
         q = 1e-5 + (1.0 - 2e-5) * sub.random(n)
         v = -BOX_VBAR * np.log1p(-q)
-        xi = np.full(n, int((BOX_N0 * BOX_DV) // n), dtype=np.uint64)
+        xi = np.full(n, int((BOX_N0 * BOX_DV) // max(n, 1)), dtype=np.uint64)
         kid = GOLOVIN if r % 2 == 0 else GEOMETRIC
         kp = [GOLOVIN_B, 0.0, 0.0, 0.0] if kid == GOLOVIN else [1.0, 0.0, 0.0, 0.0]
         runs.append(dict(n_sd=n, xi=xi, attr=v[None, :].copy(), kernel_id=kid,

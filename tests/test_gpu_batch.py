@@ -28,7 +28,7 @@ def _sync():
     torch.cuda.synchronize()
 
 
-SMALL_SIZES = [1, 2, 3, 7, 64, 255, 256, 1000, 2049, 4097, 9000, 300, 17, 5000, 12000, 2]
+SMALL_SIZES = [1, 2, 3, 7, 64, 255, 256, 1000, 2049, 4097, 9000, 0, 300, 17, 5000, 12000, 2]
 
 
 def _small_ensemble(scale=300.0):

@@ -252,3 +252,36 @@ def test_checkpoint_resume_equals_uninterrupted(sdm):
     for name in ("xi", "attr", "idx", "cell_start", "n_live"):
         assert np.array_equal(host(getattr(a, name)), host(getattr(c, name))), name
     ctx2.close()
+
+
+def test_empty_and_all_dead_states(sdm):
+    """No SDs at all, and SDs that are all dead (xi = 0): the step succeeds
+    with no live SDs, empty cells and no pairs, as the oracle says."""
+    import torch
+    ctx = sdm.Context(128, 4, 1)
+    st = sdm.State(np.zeros(0, np.uint64), np.zeros((1, 0)), None, 1)
+    ctx.step(st, 1.0, sdm.kernel(0, [1500.0]), sdm.rng(1, 0, 0), dv=1e6)
+    _sync()
+    assert int(host(st.n_live)[0]) == 0
+    assert np.array_equal(host(st.cell_start), [0, 0])
+    w = workloads.grid(seed=2, nx=2, ny=2)
+    xi = np.zeros(w["n_sd"], np.uint64)
+    ctx2 = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    _run_pair(sdm, ctx2, dict(w, xi=xi), 2, seed=5)
+    ctx.close()
+    ctx2.close()
+
+
+def test_largest_single_plan_and_the_limit(sdm):
+    """2^25 SDs in one cell (the most one plan takes: 2048 tiles of 16384
+    slots), one step element by element against the oracle; one slot pair
+    more is refused with a clean error, not a fault."""
+    n_sd = 1 << 25
+    w = workloads.box(n_sd, seed=6)
+    ctx = sdm.Context(n_sd + 2, 1, 1)
+    _run_pair(sdm, ctx, w, 1, seed=6, gamma=False)
+    big = workloads.box(n_sd + 2, seed=6)
+    st = sdm.State(big["xi"], big["attr"], None, 1)
+    with pytest.raises(sdm.SdmError):
+        ctx.step(st, 1.0, sdm.kernel(0, [1500.0]), sdm.rng(6, 0, 0), dv=1e6)
+    ctx.close()
