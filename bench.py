@@ -15,6 +15,10 @@ Workloads (--workload, default box):
   ensemble   1024 independent boxes of 2^8..2^16 SDs (log-uniform), Golovin
              and gravitational kernels alternating, advanced together
              (sdm_batch_step) with the autotuned schedule.
+  golovin    the paper's validation run itself: the box with 2^13 SDs (seed 1)
+             for 3600 steps from its initial state, timed as graph replays of
+             1200 steps; moments at 1200, 2400 and 3600 s against the Golovin
+             closed form (eq. 7 moments).
   surrogate  the moment surrogate's step for the 16384 cells of the grid
              (features, hull test, bf16 MFMA forward, moment update), beside
              one SDM step of the same grid (cell-steps/s of both).
@@ -372,6 +376,90 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     return out
 
 
+def golovin_moments(t, N0, b, vbar):
+    """Moments of the additive-kernel solution from an exponential start
+    (eq. 7): M0 = N0 (1 - tau), M1 = N0 vbar, M2 = 2 N0 vbar^2 / (1 - tau)^2,
+    tau = 1 - exp(-N0 b vbar t)."""
+    import math
+    tau = 1.0 - math.exp(-N0 * b * vbar * t)
+    return N0 * (1.0 - tau), N0 * vbar, 2.0 * N0 * vbar ** 2 / (1.0 - tau) ** 2
+
+
+def bench_golovin(args, sdm, torch, np, workloads):
+    n_sd = 1 << 13
+    w = workloads.box(n_sd, seed=1)
+    ctx = sdm.Context(n_sd, 1, 1)
+    st = sdm.State(w["xi"], w["attr"], None, 1)
+    k = sdm.kernel(w["kernel_id"], w["kparams"])
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    r = sdm.rng(1, 0, 0, step_dev=step_dev)
+    kw = dict(dv=w["dv"][0], step_advance=step_dev)
+    ctx.prepare_step(st, w["dt"], k, r, **kw)
+    stream = torch.cuda.Stream()
+    seg = 1200
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            for _ in range(seg):
+                ctx.step(st, w["dt"], k, r, stream=stream, **kw)
+    torch.cuda.synchronize()
+    # capture does not run the steps: reset the state and the step index
+    st2 = sdm.State(w["xi"], w["attr"], None, 1)
+    st.xi.copy_(st2.xi)
+    st.attr.copy_(st2.attr)
+    st.counters.zero_()
+    step_dev.zero_()
+    M = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    out_m = []
+    total_ms = 0.0
+    for t_end in (1200, 2400, 3600):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        ctx.moments(M, st.xi, st.attr[0], st.idx, st.cell_start, 1, dv=w["dv"][0])
+        torch.cuda.synchronize()
+        m = M.cpu().numpy()[0]
+        ref = golovin_moments(float(t_end), w["N0"], w["b"], w["vbar"])
+        out_m.append({"t_s": t_end, "M0_rel_err": float(m[0] / ref[0] - 1.0),
+                      "M1_rel_err": float(m[1] / ref[1] - 1.0),
+                      "M2_rel_err": float(m[2] / ref[2] - 1.0)})
+    del g
+    K = 3 * seg
+    assert int(step_dev.item()) == K and ctx.read_errors() == 0
+    out = base_line("SDM pair-steps/s, 2^13-SD Golovin box over 3600 s",
+                    (n_sd // 2) * K / (total_ms / 1e3), "pair-steps/s", K, 0, total_ms / K,
+                    "f64", {"workload": "golovin_box_2_13_3600s", "n_sd": n_sd, "cells": 1,
+                            "kernel": "golovin", "b_per_s": w["b"], "dt_s": w["dt"], "seed": 1,
+                            "timing": "three graph replays of 1200 steps"})
+    out["wall_s_3600_steps"] = total_ms / 1e3
+    out["golovin_moments"] = out_m
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        import oracle
+        s_ = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
+        steps = 600
+        t0 = time.perf_counter()
+        for t in range(steps):
+            s_ = oracle.step(s_["xi"], s_["attr"], None, 1, w["dv"], s_["idx"], s_["n_live"],
+                             dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
+                             seed=1, run=0, step=t)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": (n_sd // 2) * steps / dt, "unit": "pair-steps/s",
+                               "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "the first %d of the 3600 steps, oracle (plain C, one "
+                                         "thread)" % steps}
+    ctx.close()
+    return out
+
+
 def bench_surrogate(args, sdm, torch, np, workloads):
     """Surrogate step for every cell of the grid vs one SDM step of the grid
     (static cells), both on the GPU; random-init weights (the arithmetic per
@@ -476,7 +564,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="box", choices=["box", "grid", "ensemble", "surrogate"])
+    ap.add_argument("--workload", default="box",
+                    choices=["box", "grid", "ensemble", "golovin", "surrogate"])
     ap.add_argument("--log2-n-sd", type=int, default=22)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -509,7 +598,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     fn = {"box": bench_box, "grid": bench_grid, "ensemble": bench_ensemble,
-          "surrogate": bench_surrogate}[args.workload]
+          "golovin": bench_golovin, "surrogate": bench_surrogate}[args.workload]
     out = fn(args, sdm, torch, np, workloads)
     print(json.dumps(out), flush=True)
 

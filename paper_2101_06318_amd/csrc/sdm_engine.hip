@@ -10,8 +10,7 @@
 //            (cell, top key bits); an LDS counting sort by bucket, then the
 //            tile's records (key, s, xi, v) are written contiguously through
 //            LDS staging, with the tile's per-bucket offsets.  No global
-//            atomics except one per tile (live total) and one per (tile, big
-//            cell).
+//            atomics except one per tile (live total).
 //  k_colsum, k_bscan
 //            bucket totals (column sums of the tile offsets) and their
 //            exclusive scan: the global start rank of every bucket, hence of
@@ -79,14 +78,11 @@ struct TileArgs {
     const uint32_t *seg_off;
     const uint32_t *seg_len;
     const int32_t *seg_run;
-    const int32_t *big_cells;
-    int32_t n_big;
     uint16_t *tile_off;
     RecK *rec_k;           // list modes: (key, id)
     uint32_t *rec_s;       // fused mode: id (the key is recomputed from it)
     RecX *rec_x;           // fused mode: (xi, v)
     uint32_t chunk;        // 16-B records per LDS staging pass
-    uint32_t *cell_tot;
     uint32_t *n_acc;
     uint32_t *err;
 };
@@ -102,7 +98,6 @@ struct GroupArgs {
     const uint8_t *sub_bits;
     const int32_t *cell_h;
     const int32_t *cell_bucket_base;
-    const uint8_t *cell_big;
     const uint16_t *tile_offT;  // [B+1][n_tiles]
     const RecK *rec_k;
     const uint32_t *rec_s;
@@ -171,9 +166,6 @@ struct FinishArgs {
     int slot_cell_local;
     uint64_t *counters;
     double *gamma_out;
-    const int32_t *big_cells;
-    int32_t n_big;
-    uint32_t *cell_tot;
     uint32_t *n_acc;
     uint32_t *cell_start;
     int64_t *n_live_out;
@@ -480,12 +472,6 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     uint16_t *toff = a.tile_off + (int64_t)blockIdx.x * (B + 1);
     for (int b = tid; b <= B; b += THREADS)
         toff[b] = (uint16_t)hist[b];
-    for (int i = tid; i < a.n_big; i += THREADS) {
-        const int c = a.big_cells[i];
-        const uint32_t cnt = hist[a.cell_bucket_base[c + 1]] - hist[a.cell_bucket_base[c]];
-        if (cnt)
-            atomicAdd(&a.cell_tot[c], cnt);
-    }
     const uint32_t total = hist[B];
     uint32_t pos[EPT];
 #pragma unroll
@@ -1188,8 +1174,6 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
     if (a.mode == MODE_FUSED && a.counters)
         flush_stats<THREADS>(st, a.counters, red);
     if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < a.n_big; i += THREADS)
-            a.cell_tot[a.big_cells[i]] = 0;
         if (threadIdx.x == 0) {
             const uint32_t n = a.n_acc[0];
             *a.n_live_out = (int64_t)n;
@@ -1342,15 +1326,6 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             }
             group_first.push_back(B);
         }
-        std::vector<uint8_t> cell_big(C, 0);
-        std::vector<int32_t> big_cells;
-        for (int32_t c = 0; c < C; ++c) {
-            if (cell_bb[c + 1] > cell_bb[c] &&
-                group_of_bucket[cell_bb[c]] != group_of_bucket[cell_bb[c + 1] - 1]) {
-                cell_big[c] = 1;
-                big_cells.push_back(c);
-            }
-        }
         p->tile = TILE_THREADS * TILE_EPT;
         p->chunk = tile_chunk_for(B, p->tile);
         if (p->chunk == 0)
@@ -1360,11 +1335,8 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             throw HipError{hipErrorInvalidValue, "too many SD slots for one plan"};
         p->B = B;
         p->G = (int32_t)group_first.size() - 1;
-        p->n_big = (int32_t)big_cells.size();
         p->cell_h = upload(p, cell_h);
         p->cell_bucket_base = upload(p, cell_bb);
-        p->cell_big = upload(p, cell_big);
-        p->big_cells = upload(p, big_cells);
         p->bucket_cell = upload(p, bucket_cell);
         p->sub_bits = upload(p, sub_bits);
         p->group_first = upload(p, group_first);
@@ -1378,7 +1350,6 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         } else {
             p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
         }
-        p->cell_tot = (uint32_t *)dalloc(p, 4ull * C);
         p->n_acc = (uint32_t *)dalloc(p, 64);
         p->bucket_tot = (uint32_t *)dalloc(p, 4ull * B);
         p->bucket_start = (uint32_t *)dalloc(p, 4ull * (B + 1));
@@ -1392,7 +1363,6 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->seam_state = (uint32_t *)dalloc(p, 4ull * p->G);
         p->group_tot = (uint32_t *)dalloc(p, 4ull * p->G);
         p->group_stats = (uint32_t *)dalloc(p, 20ull * p->G);
-        SDM_HIP(hipMemset(p->cell_tot, 0, 4ull * C));
         SDM_HIP(hipMemset(p->n_acc, 0, 64));
         SDM_HIP(hipMemset(p->seam_state, 0, 4ull * p->G));
         SDM_HIP(hipMemset(p->group_tot, 0, 4ull * p->G));
@@ -1515,14 +1485,11 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.seg_off = p->seg_off;
     ta.seg_len = p->seg_len;
     ta.seg_run = p->seg_run;
-    ta.big_cells = p->big_cells;
-    ta.n_big = p->n_big;
     ta.tile_off = p->tile_off;
     ta.rec_k = p->rec_k;
     ta.rec_s = p->rec_s;
     ta.rec_x = p->rec_x;
     ta.chunk = p->chunk;
-    ta.cell_tot = p->cell_tot;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
     const size_t lds = (size_t)tile_hist_bytes(p->B) + (size_t)p->chunk * sizeof(RecK);
@@ -1558,7 +1525,6 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.sub_bits = p->sub_bits;
     ga.cell_h = p->cell_h;
     ga.cell_bucket_base = p->cell_bucket_base;
-    ga.cell_big = p->cell_big;
     ga.tile_offT = p->tile_offT;
     ga.rec_k = p->rec_k;
     ga.rec_s = p->rec_s;
@@ -1630,9 +1596,6 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     fa.slot_cell_local = in.slot_cell_local ? 1 : 0;
     fa.counters = in.counters;
     fa.gamma_out = in.gamma_out;
-    fa.big_cells = p->big_cells;
-    fa.n_big = p->n_big;
-    fa.cell_tot = p->cell_tot;
     fa.n_acc = p->n_acc;
     fa.cell_start = cell_start;
     fa.n_live_out = n_live_out;

@@ -86,13 +86,12 @@ struct SeamRec {
 };
 
 // Bucketed sort plan.  The live SDs of cell c are split by the top h[c]
-// bits of their 53-bit shuffle key into 2^h[c] buckets.  The scatter
-// kernel sorts each tile of T SD slots by bucket in LDS and writes the
-// tile's records contiguously, with its per-bucket offsets; a group of
-// consecutive buckets is then gathered from every tile and sorted by one
-// workgroup.  Cells whose buckets span several groups ("big" cells) get
-// their live count from per-tile atomics and their start rank from the
-// group holding their first bucket.
+// bits of their 53-bit shuffle key into 2^h[c] buckets.  The tile kernel
+// sorts each tile of T SD slots by bucket in LDS and writes the tile's
+// records contiguously, with its per-bucket offsets; the scan kernels turn
+// the offsets into the global start rank of every bucket (hence of every
+// group and cell); a group of consecutive buckets is then gathered from
+// every tile and sorted by one workgroup.
 struct Plan {
     int mode = 0;
     int64_t n_items = 0;  // SD slots (fused) or index capacity (list modes)
@@ -100,12 +99,9 @@ struct Plan {
     int32_t B = 0, G = 0;
     int32_t tile = 0;     // SD slots per scatter tile
     int32_t n_tiles = 0;
-    int32_t n_big = 0;
     // device tables
     int32_t *cell_h = nullptr;            // [C]
     int32_t *cell_bucket_base = nullptr;  // [C+1]
-    uint8_t *cell_big = nullptr;          // [C]
-    int32_t *big_cells = nullptr;         // [n_big]
     int32_t *bucket_cell = nullptr;       // [B]
     uint8_t *sub_bits = nullptr;          // [B]
     int32_t *group_first = nullptr;       // [G+1]
@@ -124,7 +120,6 @@ struct Plan {
     uint32_t *rec_s = nullptr;            // fused mode: id
     RecX *rec_x = nullptr;                // fused mode: (xi, v)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
-    uint32_t *cell_tot = nullptr;         // [C] (big cells; zero between launches)
     uint32_t *n_acc = nullptr;            // [0] live total [1] unused [2] unused [3] finish ticket
     uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
     uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
