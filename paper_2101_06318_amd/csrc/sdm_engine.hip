@@ -848,6 +848,12 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t t_cs[MAXB];
     __shared__ uint32_t t_n[MAXB];
     __shared__ PairCtx t_pc[MAXB];
+    // cells of the group (c_lo + i): first bucket, key bits, run and, for
+    // batches, first SD slot
+    __shared__ uint32_t g_cbb[MAXB];
+    __shared__ uint32_t g_ch[MAXB];
+    __shared__ uint32_t g_run[MAXB];
+    __shared__ uint32_t g_seg[MAXB + 1];
     __shared__ uint32_t sub_hist[NSUB + 1];
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
@@ -881,6 +887,18 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     }
     for (int i = tid; i <= nb; i += THREADS)
         t_off[i] = a.bucket_start[b0 + i] - rank0;
+    const int c_lo = a.bucket_cell[b0];
+    const int n_gc = a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
+    for (int i = tid; i <= n_gc; i += THREADS) {
+        const int c = c_lo + i;
+        if (i < n_gc) {
+            g_cbb[i] = (uint32_t)a.cell_bucket_base[c];
+            g_ch[i] = (uint32_t)a.cell_h[c];
+            g_run[i] = a.seg_run ? (uint32_t)a.seg_run[c] : a.run;
+        }
+        if (a.seg_off)
+            g_seg[i] = a.seg_off[c];
+    }
     for (int i = tid; i < nb; i += THREADS) {
         const int b = b0 + i;
         const int c = a.bucket_cell[b];
@@ -956,13 +974,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 }
             }
         }
-        if (fused) {
-            const uint32_t step = step_of(a.step, a.step_dev);
-#pragma unroll
-            for (int e = 0; e < EPT; ++e)
-                if ((uint32_t)(e * THREADS + tid) < tot)
-                    key[e] = shuffle_key(a, sid[e], step);
-        }
+        const uint32_t step = step_of(a.step, a.step_dev);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
@@ -970,7 +982,19 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             blk[e] = 0;
             fp[e] = 0;
             if (li < tot) {
-                const uint32_t bl = local_bucket(a, b0, nb, key[e], sid[e]);
+                // the record's cell among the group's cells
+                int cl = 0;
+                if (a.seg_off)
+                    cl = upper_index(g_seg, n_gc, sid[e]);
+                else if (a.cell_id && n_gc > 1)
+                    cl = a.cell_id[sid[e]] - c_lo;
+                if (fused) {
+                    const uint64_t el = a.seg_off ? (uint64_t)(sid[e] - g_seg[cl]) : sid[e];
+                    key[e] = philox_word(a.seed, g_run[cl], step, SDM_STREAM_SHUFFLE, el) >> 11;
+                }
+                const uint32_t h = g_ch[cl];
+                const uint32_t bl = g_cbb[cl] - (uint32_t)b0 +
+                                    (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
                 blk[e] = (uint8_t)bl;
                 sbk[e] = t_subbase[bl] + sub;
@@ -1056,7 +1080,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         __syncthreads();
 
         // 4. pairs opened by this thread's records: eq. (3), gamma, eqs. (4)-(6)
-        const uint32_t step = step_of(a.step, a.step_dev);
         Stats st{0, 0, 0, 0, 0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
