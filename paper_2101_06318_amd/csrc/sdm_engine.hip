@@ -39,7 +39,8 @@
 namespace sdm {
 
 constexpr int TILE_THREADS = 1024;
-constexpr int TILE_EPT = 16;      // SD slots per tile thread
+constexpr int TILE_EPT_MAX = 16;  // SD slots per tile thread (4, 8 or 16 per plan)
+constexpr int TILE_FILL = 256;    // tiles that fill the GPU (one per CU)
 constexpr int GROUP_THREADS = 512;
 constexpr int GROUP_EPT = 8;
 constexpr int MAXB = 64;             // buckets per group
@@ -1349,7 +1350,17 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             }
             group_first.push_back(B);
         }
-        p->tile = TILE_THREADS * TILE_EPT;
+        // the largest tile that still gives every CU a tile (longer runs for
+        // the groups), at least 4 slots per thread; a tile's bucket table
+        // (scan, offsets) costs in proportion to B, so smaller tiles only
+        // while B stays well below the tile size
+        int ept = TILE_EPT_MAX;
+        while (ept > 4 &&
+               (n_items + (int64_t)TILE_THREADS * ept - 1) / ((int64_t)TILE_THREADS * ept) <
+                   TILE_FILL &&
+               2 * (int64_t)B <= (int64_t)TILE_THREADS * (ept / 2))
+            ept /= 2;
+        p->tile = TILE_THREADS * ept;
         p->chunk = tile_chunk_for(B, p->tile);
         if (p->chunk == 0)
             throw HipError{hipErrorInvalidValue, "bucket table exceeds the tile LDS budget"};
@@ -1477,6 +1488,17 @@ static void launch_tile(int grid, size_t lds, hipStream_t stream, const TileArgs
                        stream, ta);
 }
 
+template <bool LIST>
+static void launch_tile_ept(int ept, int grid, size_t lds, hipStream_t stream, const TileArgs &ta)
+{
+    if (ept == 16)
+        launch_tile<16, LIST>(grid, lds, stream, ta);
+    else if (ept == 8)
+        launch_tile<8, LIST>(grid, lds, stream, ta);
+    else
+        launch_tile<4, LIST>(grid, lds, stream, ta);
+}
+
 void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
 {
     const bool list = p->mode != MODE_FUSED;
@@ -1518,9 +1540,9 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     const size_t lds = (size_t)tile_hist_bytes(p->B) + (size_t)p->chunk * sizeof(RecK);
     mark(0);
     if (list)
-        launch_tile<TILE_EPT, true>(p->n_tiles, lds, stream, ta);
+        launch_tile_ept<true>(p->tile / TILE_THREADS, p->n_tiles, lds, stream, ta);
     else
-        launch_tile<TILE_EPT, false>(p->n_tiles, lds, stream, ta);
+        launch_tile_ept<false>(p->tile / TILE_THREADS, p->n_tiles, lds, stream, ta);
     SDM_HIP(hipGetLastError());
     {
         ScanArgs sa{};
