@@ -120,7 +120,7 @@ struct Plan {
     uint32_t *rec_s = nullptr;            // fused mode: id
     RecX *rec_x = nullptr;                // fused mode: (xi, v)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
-    uint32_t *n_acc = nullptr;            // [0] live total [1] unused [2] unused [3] finish ticket
+    uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
     uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
     uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
     uint32_t *cell_start_ws = nullptr;    // [C+1]

@@ -11,14 +11,16 @@ and judges its error.  Every arithmetic step (particle steps, moments,
 features, hull test, forward, backward, loss, Adam, moment update) runs in
 the HIP library; torch holds device memory and draws minibatch orders.
 
-Workloads (seeded, synthetic):
+Workloads (seeded, synthetic), for a surrogate step of m seconds:
   * grid: 128 x 128 cells of the gravitational-kernel grid (static cells:
-    every cell is an independent box), dt in {1, 2, 5} s over 600 s;
+    every cell is an independent box), dt = 1 s over 600 s, tendencies over
+    m seconds;
   * ensemble: the 1024 Golovin / gravitational boxes of 2^8..2^16 SDs,
-    dt = 1 s over 600 s.
-Evaluation: the grid with dt = 1 s for 600 s; the reference is the mean
-over a 16-member SDM ensemble (seeds 1001..1016) of each cell's moments; a
-further member (seed 1017) gives the error of a single particle run.
+    dt = 1 s over 600 s, tendencies over m seconds.
+Evaluation: SDM on the grid with dt = 1 s for 600 s, the surrogate in steps
+of m seconds; the reference is the mean over a 16-member SDM ensemble
+(seeds 1001..1016) of each cell's moments; a further member (seed 1017)
+gives the error of a single particle run.
 """
 from __future__ import annotations
 
@@ -43,58 +45,57 @@ def _sorted_by_cell(ctx, st):
     ctx.cell_sort(st.cell_start, st.idx, st.n_live, st.cell_id, st.n_cell)
 
 
-def grid_pairs(ctx, torch, seed, dt, t_end=600.0, every=1, nx=128):
-    """(M before, M after) of every cell at every `every`-th step of one
-    static-cell grid run; returns raw features and targets (host arrays)."""
+def grid_pairs(ctx, torch, seed, lags=(1, 10), t_end=600.0, stride=10, nx=128, dt=1.0):
+    """One static-cell grid run at dt; for every lag K the pairs (moments at
+    step t, moments at step t + K) for t = 0, stride, 2 stride, ... give the
+    raw features (log M(t), K dt, kernel id) and the relative tendencies over
+    K dt.  Returns {K: (X, T)} (host arrays)."""
     w = workloads.grid(seed=seed, nx=nx, ny=nx)
     n_cell = w["n_cell"]
     st = State(w["xi"], w["attr"], w["cell_id"], n_cell)
     dvc = torch.as_tensor(np.asarray(w["dv"], np.float64)).cuda()
     k = kernel(w["kernel_id"], w["kparams"])
     _sorted_by_cell(ctx, st)
-    X, T = [], []
-    M = _moments(ctx, torch, st, n_cell, dvc)
     n_steps = int(round(t_end / dt))
+    hist = [_moments(ctx, torch, st, n_cell, dvc)]
     for t in range(n_steps):
         ctx.step(st, dt, k, rng(seed, 0, t), dv_per_cell=dvc)
-        M1 = _moments(ctx, torch, st, n_cell, dvc)
-        if t % every == 0:
-            X.append(_raw_features(torch, M, dt, w["kernel_id"]))
-            T.append(((M1 - M) / (M * dt)).cpu().numpy())
-        M = M1
-    return np.concatenate(X), np.concatenate(T)
+        hist.append(_moments(ctx, torch, st, n_cell, dvc))
+    kid = torch.full((n_cell,), float(w["kernel_id"]), dtype=torch.float64, device="cuda")
+    return _lag_pairs(torch, hist, kid, lags, stride, dt)
 
 
-def ensemble_pairs(ctx_big, torch, seed, dt=1.0, t_end=600.0, every=2, n_runs=1024):
+def ensemble_pairs(ctx_big, torch, seed, lags=(1, 10), t_end=600.0, stride=10, n_runs=1024,
+                   dt=1.0):
+    """The batched ensemble (every run a box), pairs at several lags as in
+    grid_pairs; moments from the state after each step."""
     ens = workloads.ensemble(seed=seed, n_runs=n_runs)
     xi, attr, segs = workloads.ensemble_layout(ens)
     st = State(xi, attr, None, len(segs))
     ctx = Context(st.n_sd, len(segs), 1)
     b = Batch(ctx, segs)
-    kid = torch.as_tensor(np.array([s[3] for s in segs], np.float64)).cuda()
-    X, T = [], []
-    M = None
+    kid = torch.as_tensor(np.array([s_[3] for s_ in segs], np.float64)).cuda()
     n_steps = int(round(t_end / dt))
+    hist = []
     for t in range(n_steps):
         b.step(st, dt, rng(seed, 0, t))
-        # after a step idx / cell_start hold the runs' live SDs; moments of
-        # the state before the next step
-        M1 = _moments(ctx, torch, st, len(segs), dv=workloads.BOX_DV)
-        if M is not None and t % every == 0:
-            raw = torch.stack([torch.log(M[:, 0]), torch.log(M[:, 1]), torch.log(M[:, 2]),
-                               torch.full_like(M[:, 0], dt), kid], 1)
-            X.append(raw.cpu().numpy())
-            T.append(((M1 - M) / (M * dt)).cpu().numpy())
-        M = M1
+        hist.append(_moments(ctx, torch, st, len(segs), dv=workloads.BOX_DV))
     b.close()
     ctx.close()
-    return np.concatenate(X), np.concatenate(T)
+    return _lag_pairs(torch, hist, kid, lags, stride, dt)
 
 
-def _raw_features(torch, M, dt, kernel_id):
-    return torch.stack([torch.log(M[:, 0]), torch.log(M[:, 1]), torch.log(M[:, 2]),
-                        torch.full_like(M[:, 0], float(dt)),
-                        torch.full_like(M[:, 0], float(kernel_id))], 1).cpu().numpy()
+def _lag_pairs(torch, hist, kid, lags, stride, dt):
+    out = {}
+    for K in lags:
+        X, T = [], []
+        for t in range(0, len(hist) - K, stride):
+            M, M1 = hist[t], hist[t + K]
+            X.append(torch.stack([torch.log(M[:, 0]), torch.log(M[:, 1]), torch.log(M[:, 2]),
+                                  torch.full_like(M[:, 0], K * dt), kid], 1).cpu().numpy())
+            T.append(((M1 - M) / (M * (K * dt))).cpu().numpy())
+        out[K] = (np.concatenate(X), np.concatenate(T))
+    return out
 
 
 class Surrogate:
@@ -175,11 +176,12 @@ def train(ctx, torch, Xraw, Traw, epochs=20, batch=4096, lr=1e-3, seed=7, log=No
 
 
 def evaluate(ctx, torch, sur, seeds=range(1001, 1017), held_out=1017, t_end=600.0, dt=1.0,
-             nx=128, grid_seed=3):
+             nx=128, grid_seed=3, sur_every=1):
     """Surrogate vs SDM ensemble mean on the static-cell grid.  Every member
     and the surrogate start from the same initial state (grid seed); members
-    differ in their Philox seed.  Fallback cells take the held-out member's
-    particle-method tendency for that step."""
+    differ in their Philox seed.  The surrogate takes steps of sur_every * dt;
+    fallback cells take the held-out member's particle-method tendency over
+    that step."""
     w = workloads.grid(seed=grid_seed, nx=nx, ny=nx)
     n_cell = w["n_cell"]
     dvc = torch.as_tensor(np.asarray(w["dv"], np.float64)).cuda()
@@ -200,8 +202,8 @@ def evaluate(ctx, torch, sur, seeds=range(1001, 1017), held_out=1017, t_end=600.
         return M0, M
 
     ens = []
-    for s in seeds:
-        _, Mf = member(s)
+    for s_ in seeds:
+        _, Mf = member(s_)
         ens.append(Mf)
     ens = torch.stack(ens)
     M_ens = ens.mean(0)
@@ -214,17 +216,21 @@ def evaluate(ctx, torch, sur, seeds=range(1001, 1017), held_out=1017, t_end=600.
                 y=torch.zeros((n_cell, 3), dtype=torch.float32, device="cuda"),
                 fb=torch.zeros(n_cell, dtype=torch.uint8, device="cuda"))
     counters = torch.zeros(8, dtype=torch.int64, device="cuda")
+    dt_sur = sur_every * dt
 
     def hook(t, Mp, Mp1):
         if "M" not in state:
             state["M"] = Mp.clone()
+            state["Mref"] = Mp.clone()   # the held-out member at the last surrogate step
+        if (t + 1) % sur_every:
+            return
         Ms = state["M"]
         before = Ms.clone()
-        fb = sur.step(torch, Ms, dt, w["kernel_id"], bufs, counters=counters)
+        fb = sur.step(torch, Ms, dt_sur, w["kernel_id"], bufs, counters=counters)
         sel = fb.bool()
         if bool(sel.any()):
-            # particle tendency of the held-out member for the fallback cells
-            Ms[sel] = before[sel] * (Mp1[sel] / Mp[sel])
+            Ms[sel] = before[sel] * (Mp1[sel] / state["Mref"][sel])
+        state["Mref"] = Mp1.clone()
 
     _, M_single = member(held_out, hook)
     M_sur = state["M"]
@@ -232,41 +238,57 @@ def evaluate(ctx, torch, sur, seeds=range(1001, 1017), held_out=1017, t_end=600.
     def rel_err(A):
         return (torch.abs(A - M_ens) / M_ens).mean(0).cpu().numpy()
 
-    fallback_frac = int(counters[5].item()) / float(n_cell * n_steps)
+    def domain_err(A):
+        # error of the domain mean (the sum over cells): the surrogate's bias
+        # without the per-cell sampling noise of a finite ensemble
+        return (torch.abs(A.sum(0) - M_ens.sum(0)) / M_ens.sum(0)).cpu().numpy()
+
+    fallback_frac = int(counters[5].item()) / float(n_cell * (n_steps // sur_every))
     return dict(err_surrogate=rel_err(M_sur).tolist(), err_single_sdm=rel_err(M_single).tolist(),
+                domain_err_surrogate=domain_err(M_sur).tolist(),
+                domain_err_single_sdm=domain_err(M_single).tolist(),
                 ensemble_mean_rel_sem=sem.tolist(), fallback_fraction=fallback_frac,
-                members=int(ens.shape[0]), t_end=t_end, cells=n_cell)
+                members=int(ens.shape[0]), t_end=t_end, cells=n_cell, dt_surrogate=dt_sur)
 
 
-def pipeline(torch, log=print, grid_dts=(1.0, 2.0, 5.0), epochs=20, nx=128, eval_members=16,
-             ensemble=True, t_end=600.0):
-    """Generates about 1e6 cell-steps, trains, evaluates; returns a report."""
+def pipeline(torch, log=print, epochs=20, nx=128, eval_members=16, ensemble=True, t_end=600.0,
+             grid_seeds=(100, 101, 102), eval_every=(1, 10), stride=None):
+    """For each surrogate step m dt in eval_every (dt = 1 s): pairs at lag m
+    from three grid runs and the ensemble (about 3e6 cell-steps), a network
+    trained on them, and its evaluation at that step.  One network per step
+    size: fitted jointly over several lags, the low-noise long-lag targets
+    (where runaway growth has already sped up the rates) pull the short-lag
+    prediction up.  Returns (report, {m: surrogate}, context)."""
     if log is None:
         def log(_msg):
             return None
     w = workloads.grid(seed=3, nx=nx, ny=nx)
     ctx = Context(w["n_sd"] + 1024, max(w["n_cell"], 1024), 2)
-    Xs, Ts = [], []
-    for i, dt in enumerate(grid_dts):
-        steps = int(round(t_end / dt))
-        every = max(1, steps // 15)
-        X, T = grid_pairs(ctx, torch, seed=100 + i, dt=dt, t_end=t_end, every=every, nx=nx)
-        log("grid dt=%g: %d samples" % (dt, len(X)))
-        Xs.append(X)
-        Ts.append(T)
+    lags = tuple(eval_every)
+    data = {K: ([], []) for K in lags}
+    if stride is None:
+        stride = max(1, int(round(t_end / 60)))
+    parts = [grid_pairs(ctx, torch, seed=sd, lags=lags, t_end=t_end, stride=stride, nx=nx)
+             for sd in grid_seeds]
     if ensemble:
-        X, T = ensemble_pairs(ctx, torch, seed=200, dt=1.0, t_end=t_end, every=2)
-        log("ensemble: %d samples" % len(X))
-        Xs.append(X)
-        Ts.append(T)
-    X = np.concatenate(Xs)
-    T = np.concatenate(Ts)
-    sur, losses = train(ctx, torch, X, T, epochs=epochs, log=log)
-    rep = evaluate(ctx, torch, sur, seeds=range(1001, 1001 + eval_members),
-                   held_out=1001 + eval_members, nx=nx, t_end=t_end)
-    rep["train_samples"] = int(len(X))
-    rep["losses"] = losses
-    return rep, sur, ctx
+        parts.append(ensemble_pairs(ctx, torch, seed=200, lags=lags, t_end=t_end, stride=stride))
+    for part in parts:
+        for K in lags:
+            data[K][0].append(part[K][0])
+            data[K][1].append(part[K][1])
+    rep = dict(runs=[])
+    surs = {}
+    for K in lags:
+        X = np.concatenate(data[K][0])
+        T = np.concatenate(data[K][1])
+        log("step %g s: %d samples" % (K, len(X)))
+        sur, losses = train(ctx, torch, X, T, epochs=epochs, log=log)
+        ev = evaluate(ctx, torch, sur, seeds=range(1001, 1001 + eval_members),
+                      held_out=1001 + eval_members, nx=nx, t_end=t_end, sur_every=K)
+        ev.update(train_samples=int(len(X)), losses=losses)
+        rep["runs"].append(ev)
+        surs[K] = sur
+    return rep, surs, ctx
 
 
 if __name__ == "__main__":
@@ -283,10 +305,13 @@ if __name__ == "__main__":
     ap.add_argument("--members", type=int, default=16)
     ap.add_argument("--t-end", type=float, default=600.0)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--grid-runs", type=int, default=3)
+    ap.add_argument("--stride", type=int, default=None)
     a = ap.parse_args()
     t0 = time.time()
     rep, _, _ = pipeline(torch, log=lambda m: print(m, file=sys.stderr, flush=True),
                          epochs=a.epochs, nx=a.nx, eval_members=a.members,
-                         ensemble=not a.no_ensemble, t_end=a.t_end)
+                         ensemble=not a.no_ensemble, t_end=a.t_end,
+                         grid_seeds=tuple(range(100, 100 + a.grid_runs)), stride=a.stride)
     rep["seconds"] = round(time.time() - t0, 1)
     print(json.dumps(rep), flush=True)

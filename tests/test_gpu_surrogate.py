@@ -16,12 +16,13 @@ def test_surrogate_pipeline_small():
     assert torch.cuda.is_available()
     from paper_2101_06318_amd import surrogate
     rep, sur, ctx = surrogate.pipeline(torch, log=None, epochs=10, nx=32, eval_members=8,
-                                       ensemble=False, t_end=120.0)
-    losses = rep["losses"]
-    assert rep["train_samples"] > 50000
+                                       ensemble=False, t_end=120.0, eval_every=(1,))
+    ev = rep["runs"][0]
+    losses = ev["losses"]
+    assert ev["train_samples"] > 50000
     assert losses[-1] < losses[0], losses
-    assert rep["fallback_fraction"] < 0.01, rep
-    es, e1 = rep["err_surrogate"], rep["err_single_sdm"]
+    assert ev["fallback_fraction"] < 0.01, rep
+    es, e1 = ev["err_surrogate"], ev["err_single_sdm"]
     assert es[0] < e1[0] and es[2] < e1[2], rep
     assert es[1] < 1e-12 and e1[1] < 1e-12, rep          # M1 (mass) is conserved
     assert np.all(np.isfinite(es)), rep
