@@ -81,7 +81,7 @@ struct TileArgs {
     const int32_t *seg_run;
     uint16_t *tile_off;
     RecK *rec_k;           // list modes: (key, id)
-    uint32_t *rec_s;       // fused mode: id (the key is recomputed from it)
+    uint64_t *rec_sk;      // fused mode: id | (key >> 21) << 32
     RecX *rec_x;           // fused mode: (xi, v)
     uint32_t chunk;        // 16-B records per LDS staging pass
     uint32_t *n_acc;
@@ -101,7 +101,7 @@ struct GroupArgs {
     const int32_t *cell_bucket_base;
     const uint16_t *tile_offT;  // [B+1][n_tiles]
     const RecK *rec_k;
-    const uint32_t *rec_s;
+    const uint64_t *rec_sk;
     const RecX *rec_x;
     const int32_t *cell_id;
     const uint32_t *bucket_start;
@@ -481,8 +481,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         pos[j] = b == NO_BUCKET ? 0xFFFFFFFFu : hist[b] + (bk[j] >> 16);
     }
     // staged, coalesced write-out of the tile's records in bucket order.
-    // Fused mode: ids (the group kernel recomputes the keys from them), then
-    // (xi, v); list modes: (key, id).  Passes of a.chunk 16-B records.
+    // Fused mode: id and the key's top 32 bits in one word, then (xi, v);
+    // list modes: (key, id).  Passes of a.chunk 16-B records.
     const int64_t rbase = (int64_t)blockIdx.x * T;
     const uint32_t CH = a.chunk;
     if (LIST) {  // the list modes (the fused step always runs LIST = false)
@@ -510,18 +510,20 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         }
         return;
     }
-    uint32_t *sts = reinterpret_cast<uint32_t *>(stage);
-    const uint32_t CHS = 4 * CH;  // ids per pass
+    uint64_t *sts = stage;
+    const uint32_t CHS = 2 * CH;  // id words per pass
     for (uint32_t c0 = 0; c0 < total; c0 += CHS) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
             if (pos[j] - c0 < CHS)
                 sts[pos[j] - c0] =
-                    (uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) + (j & 1));
+                    (uint64_t)(uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
+                                         (j & 1)) |
+                    ((key[j] >> 21) << 32);
         __syncthreads();
         const uint32_t n = min(CHS, total - c0);
         for (uint32_t i = tid; i < n; i += THREADS)
-            a.rec_s[rbase + c0 + i] = sts[i];
+            a.rec_sk[rbase + c0 + i] = sts[i];
         __syncthreads();
     }
     // volumes, read now as coalesced pairs (the keys are dead)
@@ -949,10 +951,13 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
                 tmap[li] = (uint16_t)t;
         __syncthreads();
+        // fused mode: key[] holds the top 32 bits of the 53-bit key (bits
+        // 52..21); they fix the bucket and sub-bucket (h + u <= 32), and the
+        // rank falls back to the whole key only between equal top bits
         uint64_t key[EPT], xv[EPT];
         double vv[EPT];
         uint32_t sid[EPT], sbk[EPT], fp[EPT];
-        uint8_t blk[EPT];
+        uint8_t blk[EPT], gcl[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
@@ -964,7 +969,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 const int t = tmap[li];
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
                 if (fused) {
-                    sid[e] = a.rec_s[pos];
+                    const uint64_t sk = a.rec_sk[pos];
+                    sid[e] = (uint32_t)sk;
+                    key[e] = (sk >> 32) << 21;
                     const RecX rx = a.rec_x[pos];
                     xv[e] = rx.xi;
                     vv[e] = rx.v;
@@ -981,6 +988,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             const uint32_t li = (uint32_t)(e * THREADS + tid);
             sbk[e] = 0xFFFFFFFFu;
             blk[e] = 0;
+            gcl[e] = 0;
             fp[e] = 0;
             if (li < tot) {
                 // the record's cell among the group's cells
@@ -989,10 +997,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                     cl = upper_index(g_seg, n_gc, sid[e]);
                 else if (a.cell_id && n_gc > 1)
                     cl = a.cell_id[sid[e]] - c_lo;
-                if (fused) {
-                    const uint64_t el = a.seg_off ? (uint64_t)(sid[e] - g_seg[cl]) : sid[e];
-                    key[e] = philox_word(a.seed, g_run[cl], step, SDM_STREAM_SHUFFLE, el) >> 11;
-                }
+                gcl[e] = (uint8_t)cl;
                 const uint32_t h = g_ch[cl];
                 const uint32_t bl = g_cbb[cl] - (uint32_t)b0 +
                                     (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
@@ -1020,7 +1025,24 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 uint32_t r = 0;
                 for (uint32_t q = lo; q < hi; ++q) {
                     const uint64_t kq = K1[q];
-                    r += (kq < key[e]) || (kq == key[e] && S1[q] < sid[e]);
+                    const uint32_t sq = S1[q];
+                    if (kq < key[e]) {
+                        ++r;
+                    } else if (kq == key[e] && sq != sid[e]) {
+                        if (fused) {
+                            // equal top bits: the whole keys (same cell, so
+                            // the same run) decide, then the ids
+                            const int cl = gcl[e];
+                            const uint32_t so = a.seg_off ? g_seg[cl] : 0u;
+                            const uint64_t km = philox_word(a.seed, g_run[cl], step,
+                                                            SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
+                            const uint64_t kx = philox_word(a.seed, g_run[cl], step,
+                                                            SDM_STREAM_SHUFFLE, sq - so) >> 11;
+                            r += (kx < km) || (kx == km && sq < sid[e]);
+                        } else {
+                            r += sq < sid[e];
+                        }
+                    }
                 }
                 fp[e] = lo + r;
             }
@@ -1121,7 +1143,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, nt, li);
         const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-        const uint32_t s = fused ? a.rec_s[pos] : a.rec_k[pos].s;
+        const uint32_t s = fused ? (uint32_t)a.rec_sk[pos] : a.rec_k[pos].s;
         const uint64_t k =
             fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
         a.sk[base2 + li] = k;
@@ -1316,8 +1338,10 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             int u = 0;
             while (e / std::ldexp(1.0, u + 1) >= 1.0 && u < 12)
                 ++u;
-            if (u > 53 - h)
-                u = 53 - h;
+            // the group kernel finds bucket and sub-bucket in the key's top
+            // 32 bits
+            if (h + u > 32)
+                throw HipError{hipErrorInvalidValue, "key bits of a bucket exceed 32"};
             for (int i = 0; i < (1 << h); ++i) {
                 bucket_cell.push_back(c);
                 sub_bits.push_back((uint8_t)u);
@@ -1379,7 +1403,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         if (fused) {
-            p->rec_s = (uint32_t *)dalloc(p, 4ull * R);
+            p->rec_sk = (uint64_t *)dalloc(p, 8ull * R);
             p->rec_x = (RecX *)dalloc(p, sizeof(RecX) * R);
         } else {
             p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
@@ -1532,7 +1556,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.seg_run = p->seg_run;
     ta.tile_off = p->tile_off;
     ta.rec_k = p->rec_k;
-    ta.rec_s = p->rec_s;
+    ta.rec_sk = p->rec_sk;
     ta.rec_x = p->rec_x;
     ta.chunk = p->chunk;
     ta.n_acc = p->n_acc;
@@ -1572,7 +1596,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_bucket_base = p->cell_bucket_base;
     ga.tile_offT = p->tile_offT;
     ga.rec_k = p->rec_k;
-    ga.rec_s = p->rec_s;
+    ga.rec_sk = p->rec_sk;
     ga.rec_x = p->rec_x;
     ga.cell_id = in.cell_id;
     ga.bucket_start = p->bucket_start;

@@ -117,7 +117,7 @@ struct Plan {
     uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
     // records in tile-local bucket order, [n_tiles * tile]
     RecK *rec_k = nullptr;                // list modes: (key, id)
-    uint32_t *rec_s = nullptr;            // fused mode: id
+    uint64_t *rec_sk = nullptr;           // fused mode: id | (key >> 21) << 32
     RecX *rec_x = nullptr;                // fused mode: (xi, v)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
