@@ -42,14 +42,14 @@ constexpr int TILE_THREADS = 1024;
 constexpr int TILE_EPT_MAX = 16;  // SD slots per tile thread (4, 8 or 16 per plan)
 constexpr int TILE_FILL = 256;    // tiles that fill the GPU (one per CU)
 constexpr int GROUP_THREADS = 512;
-constexpr int GROUP_EPT = 8;
-constexpr int MAXB = 64;             // buckets per group
-constexpr int NSUB = 4096;           // sub-buckets per group
+constexpr int GROUP_EPT_S = 6;       // records per group thread: the usual plans
+constexpr int GROUP_EPT_L = 8;       // plans whose buckets hold more than GROUP_TARGET SDs
+constexpr int MAXB = 32;             // buckets per group
 constexpr int MAX_TILES = 2048;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
 constexpr double BUCKET_TARGET = 1024.0;
-constexpr double GROUP_TARGET = 3200.0;
+constexpr double GROUP_TARGET = 2400.0;  // expected SDs per group of GROUP_EPT_S plans
 constexpr uint32_t NO_BUCKET = 0xFFFFu;
 
 __device__ __forceinline__ uint32_t load32_agent(const uint32_t *p)
@@ -200,6 +200,19 @@ __device__ __forceinline__ int upper_index(const uint32_t *tab, int n, uint32_t 
             hi = mid;
     }
     return lo;
+}
+
+// Inclusive scan over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, 64);
+        if (lane >= o)
+            v += t;
+    }
+    return v;
 }
 
 // Exclusive scan over THREADS values held one per thread.
@@ -844,6 +857,7 @@ template <int THREADS, int EPT>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
+    constexpr int NSUB = CAP;  // sub-buckets per group
     __shared__ uint32_t t_off[MAXB + 1];
     __shared__ uint32_t t_subbase[MAXB + 1];
     __shared__ uint32_t t_shift[MAXB];
@@ -851,6 +865,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t t_cs[MAXB];
     __shared__ uint32_t t_n[MAXB];
     __shared__ PairCtx t_pc[MAXB];
+    __shared__ uint32_t t_pa[MAXB];        // first opener position of each bucket
+    __shared__ uint32_t t_poff[MAXB + 1];  // pairs of the buckets before
     // cells of the group (c_lo + i): first bucket, key bits, run and, for
     // batches, first SD slot
     __shared__ uint32_t g_cbb[MAXB];
@@ -861,9 +877,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
     // gather: tile map and the group's run in every tile; sort: keys and
-    // ids by sorted position (12 B per record); afterwards the closing SD of
-    // every pair by pair slot (20 B per two records)
-    __shared__ __align__(16) unsigned char pool[CAP * 12];
+    // ids by sub-bucket position (12 B per record); afterwards the records
+    // in sorted order (fused mode: xi, v, id, 20 B per record)
+    __shared__ __align__(16) unsigned char pool[CAP * 20];
     static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 2 * MAX_TILES <= 12 * CAP,
                   "run tables must fit the sort pool");
     uint32_t *run_pre = reinterpret_cast<uint32_t *>(pool + 2 * CAP);
@@ -922,14 +938,13 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     }
     __syncthreads();
     lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, nt, red);
-    if (tid == 0) {
-        uint32_t sub = 0;
-        for (int i = 0; i < nb; ++i) {
-            const uint32_t ns = t_subbase[i];
-            t_subbase[i] = sub;
-            sub += ns;
-        }
-        t_subbase[nb] = sub;
+    if (tid < 64) {  // nb <= MAXB = 64: one wave scans the sub-bucket counts
+        const uint32_t ns = tid < nb ? t_subbase[tid] : 0u;
+        const uint32_t inc = wave_inclusive_scan(ns);
+        if (tid < nb)
+            t_subbase[tid] = inc - ns;
+        if (tid == 63)
+            t_subbase[nb] = inc;
     }
     const uint32_t cap_here =
         a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
@@ -1018,76 +1033,139 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             }
         }
         __syncthreads();
+        // rank by (key, s) inside the sub-bucket: the first RW entries of
+        // every sub-bucket with independent (predicated) loads, the rare
+        // longer ones in a loop, and equal top key bits (fused mode) by the
+        // whole keys
+        constexpr uint32_t RW = 4;
+        uint32_t rlo[EPT], rhi[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (sbk[e] != 0xFFFFFFFFu) {
-                const uint32_t lo = sub_hist[sbk[e]], hi = sub_hist[sbk[e] + 1];
-                uint32_t r = 0;
-                for (uint32_t q = lo; q < hi; ++q) {
-                    const uint64_t kq = K1[q];
+            const uint32_t sb = sbk[e] != 0xFFFFFFFFu ? sbk[e] : 0u;
+            rlo[e] = sub_hist[sb];
+            rhi[e] = sbk[e] != 0xFFFFFFFFu ? sub_hist[sb + 1] : rlo[e];
+        }
+        uint32_t tie = 0;  // bit e: record e met an equal key (other id)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uint32_t r = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < RW; ++j) {
+                const uint32_t q = min(rlo[e] + j, (uint32_t)CAP - 1u);
+                const uint64_t kq = K1[q];
+                const uint32_t sq = S1[q];
+                const bool in = rlo[e] + j < rhi[e];
+                r += in && kq < key[e];
+                if (in && kq == key[e] && sq != sid[e])
+                    tie |= 1u << e;
+            }
+            for (uint32_t q = rlo[e] + RW; q < rhi[e]; ++q) {
+                const uint64_t kq = K1[q];
+                r += kq < key[e];
+                if (kq == key[e] && S1[q] != sid[e])
+                    tie |= 1u << e;
+            }
+            fp[e] = rlo[e] + r;
+        }
+        if (tie) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                if (!((tie >> e) & 1u))
+                    continue;
+                uint64_t km = 0;
+                uint32_t so = 0, run = 0;
+                if (fused) {
+                    // equal top bits: the whole keys (same cell, so the
+                    // same run) decide, then the ids
+                    const int cl = gcl[e];
+                    so = a.seg_off ? g_seg[cl] : 0u;
+                    run = g_run[cl];
+                    km = philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
+                }
+                for (uint32_t q = rlo[e]; q < rhi[e]; ++q) {
                     const uint32_t sq = S1[q];
-                    if (kq < key[e]) {
-                        ++r;
-                    } else if (kq == key[e] && sq != sid[e]) {
-                        if (fused) {
-                            // equal top bits: the whole keys (same cell, so
-                            // the same run) decide, then the ids
-                            const int cl = gcl[e];
-                            const uint32_t so = a.seg_off ? g_seg[cl] : 0u;
-                            const uint64_t km = philox_word(a.seed, g_run[cl], step,
-                                                            SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
-                            const uint64_t kx = philox_word(a.seed, g_run[cl], step,
-                                                            SDM_STREAM_SHUFFLE, sq - so) >> 11;
-                            r += (kx < km) || (kx == km && sq < sid[e]);
-                        } else {
-                            r += sq < sid[e];
-                        }
+                    if (K1[q] != key[e] || sq == sid[e])
+                        continue;
+                    if (fused) {
+                        const uint64_t kx =
+                            philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sq - so) >> 11;
+                        fp[e] += (kx < km) || (kx == km && sq < sid[e]);
+                    } else {
+                        fp[e] += sq < sid[e];
                     }
                 }
-                fp[e] = lo + r;
             }
         }
-        __syncthreads();  // keys and ids are dead: the pool now holds pair slots
+        __syncthreads();  // keys and ids are dead
+        if (!fused) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (sbk[e] != 0xFFFFFFFFu)
+                    a.idx_out[rank0 + fp[e]] = sid[e];
+            return;
+        }
 
-        // 3. idx, closing SDs into their pair slot, seam records
-        uint64_t *CX = reinterpret_cast<uint64_t *>(pool);
-        double *CV = reinterpret_cast<double *>(pool + 4 * CAP);
-        uint32_t *CS = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
-        uint32_t opener = 0;  // bit e: record e opens a pair inside the group
-        uint32_t state = 0;
+        // 3. the records in sorted order (SoA in the pool), idx, seams
+        uint64_t *RX = reinterpret_cast<uint64_t *>(pool);
+        double *RV = reinterpret_cast<double *>(pool + 8 * CAP);
+        uint32_t *RS = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (sbk[e] == 0xFFFFFFFFu)
                 continue;
             const uint32_t f = fp[e];
-            const uint32_t r = rank0 + f;
-            a.idx_out[r] = sid[e];
-            if (!fused)
-                continue;
-            const uint32_t bl = blk[e];
-            const uint32_t cs = t_cs[bl];
-            const uint32_t ic = r - cs;
-            const bool op = ((ic & 1u) == 0u) && (ic + 1u < t_n[bl]);
-            const bool cl = (ic & 1u) != 0u;
-            if (op && f + 1 < tot) {
-                opener |= 1u << e;
-            } else if (cl && f > 0) {
-                // the pair (f - 1, f): slot f / 2 (two closers are never adjacent)
-                CX[f >> 1] = xv[e];
-                CV[f >> 1] = vv[e];
-                CS[f >> 1] = sid[e];
+            RX[f] = xv[e];
+            RV[f] = vv[e];
+            RS[f] = sid[e];
+        }
+        if (tid < 64) {
+            // pairs of every bucket: openers at even in-cell indices whose
+            // closer is in the same cell and in this group; pair k of the
+            // group opens at t_pa[b] + 2 (k - t_poff[b])
+            uint32_t cnt = 0;
+            if (tid < nb) {
+                const uint32_t lo = t_off[tid], hi = t_off[tid + 1];
+                const uint32_t cs = t_cs[tid];
+                const uint32_t fa = lo + ((rank0 + lo - cs) & 1u);
+                if (lo < hi) {
+                    // openers f < lim: f < hi, f + 1 < tot, rank0 + f + 1 < cs + n_c
+                    uint32_t lim = min(hi, tot - 1u);
+                    lim = min(lim, cs + t_n[tid] - 1u - rank0);
+                    cnt = fa < lim ? (lim - fa + 1u) >> 1 : 0u;
+                }
+                t_pa[tid] = fa;
             }
-            if ((op && f + 1 >= tot) || (cl && f == 0)) {
+            const uint32_t inc = wave_inclusive_scan(cnt);
+            if (tid < nb)
+                t_poff[tid] = inc - cnt;
+            if (tid == 63)
+                t_poff[nb] = inc;
+        }
+        __syncthreads();
+        for (uint32_t f = tid; f < tot; f += THREADS)
+            a.idx_out[rank0 + f] = RS[f];
+        if (tid == 0 && tot > 0) {
+            // a closer at position 0 and an opener at position tot - 1 pair
+            // with the neighbouring groups (k_finish)
+            uint32_t state = 0;
+            for (int end = 0; end < 2; ++end) {
+                const uint32_t f = end ? tot - 1u : 0u;
+                const int bl = upper_index(t_off, nb, f);
+                const uint32_t cs = t_cs[bl];
+                const uint32_t ic = rank0 + f - cs;
+                const bool seam = end ? ((ic & 1u) == 0u && ic + 1u < t_n[bl]) : (ic & 1u) != 0u;
+                if (!seam)
+                    continue;
                 SeamRec rec;
-                rec.xi = xv[e];
-                rec.v = vv[e];
-                rec.s = sid[e];
-                rec.rank = r;
+                rec.xi = RX[f];
+                rec.v = RV[f];
+                rec.s = RS[f];
+                rec.rank = rank0 + f;
                 rec.cell = a.bucket_cell[b0 + bl];
                 rec.cs = cs;
                 rec.n_c = t_n[bl];
                 rec.pad = 0;
-                if (op) {
+                if (end) {
                     a.seam_open[g] = rec;
                     state |= 1u;
                 } else {
@@ -1095,37 +1173,62 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                     state |= 2u;
                 }
             }
+            a.seam_state[g] = state;
+            a.group_tot[g] = tot;
         }
-        if (!fused)
-            return;
-        if (state)
-            atomicOr(&s_misc[2], state);
-        __syncthreads();
+        if (tid == 0 && tot == 0) {
+            a.seam_state[g] = 0;
+            a.group_tot[g] = 0;
+        }
 
-        // 4. pairs opened by this thread's records: eq. (3), gamma, eqs. (4)-(6)
+        // 4. pairs k = 2j, 2j + 1 per thread (adjacent pair slots share one
+        //    Philox block): eq. (3), gamma, eqs. (4)-(6)
         Stats st{0, 0, 0, 0, 0};
+        const uint32_t n_pairs = t_poff[nb];
+        for (uint32_t j = tid; 2 * j < n_pairs; j += THREADS) {
+            uint32_t qv[2] = {0, 0}, runv[2] = {0, 0}, fv[2] = {0, 0};
+            int bv[2] = {0, 0};
+            double pv[2] = {0.0, 0.0};
+            bool valid[2];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            if (!((opener >> e) & 1u))
-                continue;
-            const uint32_t f = fp[e];
-            const uint32_t c = (f + 1) >> 1;
-            const uint64_t xb = CX[c];
-            const double vb = CV[c];
-            const uint32_t sb2 = CS[c];
-            const PairCtx pc = t_pc[blk[e]];
-            const uint32_t q = (rank0 + f - pc.slot_base) >> 1;
-            const double p = pair_prob(pc, xv[e], vv[e], xb, vb);
-            const double phi =
-                word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
-            finish_pair(a, pc, q, p, phi, sid[e], xv[e], sb2, xb, st);
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t k = 2 * j + (uint32_t)u;
+                valid[u] = k < n_pairs;
+                if (!valid[u])
+                    continue;
+                const int bl = upper_index(t_poff, nb, k);
+                const uint32_t f = t_pa[bl] + 2u * (k - t_poff[bl]);
+                const PairCtx &pc = t_pc[bl];
+                bv[u] = bl;
+                fv[u] = f;
+                runv[u] = pc.run;
+                qv[u] = (rank0 + f - pc.slot_base) >> 1;
+                pv[u] = pair_prob(pc, RX[f], RV[f], RX[f + 1], RV[f + 1]);
+            }
+            double phi[2] = {0.0, 0.0};
+            if (valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1u && runv[0] == runv[1]) {
+                const WordPair wp = philox_words(a.seed, runv[0], step, SDM_STREAM_GAMMA,
+                                                 qv[0] >> 1);
+                phi[0] = word_to_uniform(wp.even);
+                phi[1] = word_to_uniform(wp.odd);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (valid[u])
+                        phi[u] = word_to_uniform(
+                            philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!valid[u])
+                    continue;
+                const uint32_t f = fv[u];
+                finish_pair(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[f], RX[f], RS[f + 1],
+                            RX[f + 1], st);
+            }
         }
         if (a.counters)
             store_group_stats<THREADS>(a, g, st, red);
-        if (tid == 0) {
-            a.seam_state[g] = s_misc[2];
-            a.group_tot[g] = tot;
-        }
         return;
     }
     const GroupTabs T{t_off, t_cs, t_n, t_pc};
@@ -1326,6 +1429,23 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         std::vector<int32_t> bucket_cell;
         std::vector<uint8_t> sub_bits;
         std::vector<double> bucket_exp;
+        // records per group thread: larger groups when a bucket alone
+        // exceeds the usual group size
+        double e_max = 0.0;
+        for (int32_t c = 0; c < C; ++c) {
+            const double m = std::max(expected[c], 1.0);
+            int h = 0;
+            while (m / std::ldexp(1.0, h) > target && h < 20)
+                ++h;
+            e_max = std::max(e_max, m / std::ldexp(1.0, h));
+        }
+        p->gept = e_max > group_target ? GROUP_EPT_L : GROUP_EPT_S;
+        if (p->gept == GROUP_EPT_L)
+            group_target *= (double)GROUP_EPT_L / GROUP_EPT_S;
+        const int nsub_max = GROUP_THREADS * p->gept;  // sub-buckets per group
+        int nsub_bits = 0;
+        while ((2 << nsub_bits) <= nsub_max)
+            ++nsub_bits;
         int32_t B = 0;
         for (int32_t c = 0; c < C; ++c) {
             const double m = std::max(expected[c], 1.0);
@@ -1336,7 +1456,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             cell_bb[c] = B;
             const double e = m / std::ldexp(1.0, h);
             int u = 0;
-            while (e / std::ldexp(1.0, u + 1) >= 1.0 && u < 12)
+            while (e / std::ldexp(1.0, u + 1) >= 1.0 && u < nsub_bits)
                 ++u;
             // the group kernel finds bucket and sub-bucket in the key's top
             // 32 bits
@@ -1363,7 +1483,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                 while (b < B) {
                     const int ns = 1 << sub_bits[b];
                     if (n > 0 && (acc + bucket_exp[b] > group_target || n + 1 > MAXB ||
-                                  nsub + ns > NSUB))
+                                  nsub + ns > nsub_max))
                         break;
                     acc += bucket_exp[b];
                     nsub += ns;
@@ -1451,8 +1571,8 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
 // Schedules the batch autotuner chooses from: (expected SDs per key bucket,
 // expected SDs per group).  Results never depend on the choice.
 static const double kSchedules[][2] = {
-    {1024.0, 3200.0}, {512.0, 3200.0}, {2048.0, 3200.0},
-    {1024.0, 2400.0}, {512.0, 2400.0}, {2048.0, 2048.0},
+    {1024.0, 2400.0}, {512.0, 2400.0}, {2048.0, 2400.0},
+    {1024.0, 1800.0}, {512.0, 1800.0}, {512.0, 1200.0},
 };
 int n_schedules() { return (int)(sizeof(kSchedules) / sizeof(kSchedules[0])); }
 
@@ -1632,8 +1752,12 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.group_tot = p->group_tot;
     ga.group_stats = p->group_stats;
     mark(1);
-    hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT>), dim3(p->G), dim3(GROUP_THREADS), 0,
-                       stream, ga);
+    if (p->gept == GROUP_EPT_L)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
     SDM_HIP(hipGetLastError());
 
     FinishArgs fa{};

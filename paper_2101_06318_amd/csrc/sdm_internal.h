@@ -120,6 +120,7 @@ struct Plan {
     uint64_t *rec_sk = nullptr;           // fused mode: id | (key >> 21) << 32
     RecX *rec_x = nullptr;                // fused mode: (xi, v)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
+    int gept = 0;                         // records per group-kernel thread (4 or 8)
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
     uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
     uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
