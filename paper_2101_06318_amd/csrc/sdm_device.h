@@ -248,6 +248,30 @@ __device__ __forceinline__ void apply_collision(const Collision &c, uint32_t sa,
     }
 }
 
+// apply_collision for a caller that holds the pair's volumes (attribute
+// row 0) already: row 0 is written without reading it back.
+__device__ __forceinline__ void apply_collision_v(const Collision &c, uint32_t sa,
+                                                  uint32_t sb, double va, double vb,
+                                                  uint64_t *xi, double *attr, int n_attr,
+                                                  int64_t stride)
+{
+    const uint32_t sj = c.a_is_j ? sa : sb;
+    const uint32_t sk = c.a_is_j ? sb : sa;
+    xi[sj] = c.xj_new;
+    xi[sk] = c.xk_new;
+    double Vj = c.a_is_j ? va : vb, Vk = c.a_is_j ? vb : va;
+    collide_attr(Vj, Vk, c.g, c.split);
+    attr[sj] = Vj;
+    attr[sk] = Vk;
+    for (int r = 1; r < n_attr; ++r) {
+        double *A = attr + (int64_t)r * stride;
+        double Aj = A[sj], Ak = A[sk];
+        collide_attr(Aj, Ak, c.g, c.split);
+        A[sj] = Aj;
+        A[sk] = Ak;
+    }
+}
+
 // Workgroup reduction of the statistics into counters[8] (one atomic per
 // nonzero slot per workgroup).  `red` is LDS scratch of 5*(threads/64) words.
 template <int THREADS>

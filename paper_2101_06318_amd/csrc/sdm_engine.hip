@@ -640,6 +640,21 @@ __device__ __forceinline__ void finish_pair(const Args &a, const PairCtx &pc, ui
         apply_collision(col, sa, sbb, a.xi, a.attr, a.n_attr, a.stride);
 }
 
+// finish_pair with the pair's volumes at hand (the group kernel's records).
+template <class Args>
+__device__ __forceinline__ void finish_pair_v(const Args &a, const PairCtx &pc, uint32_t q,
+                                              double p, double phi, uint32_t sa, uint64_t xa,
+                                              double va, uint32_t sbb, uint64_t xb, double vb,
+                                              Stats &st)
+{
+    const double gamma = ceil(p - phi);
+    if (a.gamma_out)
+        a.gamma_out[pc.gbase + q] = gamma;
+    const Collision col = collide(xa, xb, gamma, st);
+    if (col.g)
+        apply_collision_v(col, sa, sbb, va, vb, a.xi, a.attr, a.n_attr, a.stride);
+}
+
 // Per-local-bucket tables of a group, in LDS.
 struct GroupTabs {
     uint32_t *off;     // [nb+1] local offset of each bucket
@@ -1024,76 +1039,96 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
         __syncthreads();
         lds_exclusive_scan<THREADS, (NSUB + THREADS - 1) / THREADS>(sub_hist, (int)nsub, red);
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            if (sbk[e] != 0xFFFFFFFFu) {
-                const uint32_t pos = sub_hist[sbk[e]] + fp[e];
-                K1[pos] = key[e];
-                S1[pos] = sid[e];
-            }
-        }
-        __syncthreads();
         // rank by (key, s) inside the sub-bucket: the first RW entries of
         // every sub-bucket with independent (predicated) loads, the rare
-        // longer ones in a loop, and equal top key bits (fused mode) by the
-        // whole keys
+        // longer ones in a loop.  Fused mode sorts (top 32 key bits, id)
+        // words and settles equal top bits by the whole keys.
         constexpr uint32_t RW = 4;
         uint32_t rlo[EPT], rhi[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t sb = sbk[e] != 0xFFFFFFFFu ? sbk[e] : 0u;
-            rlo[e] = sub_hist[sb];
-            rhi[e] = sbk[e] != 0xFFFFFFFFu ? sub_hist[sb + 1] : rlo[e];
-        }
         uint32_t tie = 0;  // bit e: record e met an equal key (other id)
+        if (fused) {
+            uint64_t *KS = reinterpret_cast<uint64_t *>(pool);
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            uint32_t r = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < RW; ++j) {
-                const uint32_t q = min(rlo[e] + j, (uint32_t)CAP - 1u);
-                const uint64_t kq = K1[q];
-                const uint32_t sq = S1[q];
-                const bool in = rlo[e] + j < rhi[e];
-                r += in && kq < key[e];
-                if (in && kq == key[e] && sq != sid[e])
-                    tie |= 1u << e;
-            }
-            for (uint32_t q = rlo[e] + RW; q < rhi[e]; ++q) {
-                const uint64_t kq = K1[q];
-                r += kq < key[e];
-                if (kq == key[e] && S1[q] != sid[e])
-                    tie |= 1u << e;
-            }
-            fp[e] = rlo[e] + r;
-        }
-        if (tie) {
+            for (int e = 0; e < EPT; ++e)
+                if (sbk[e] != 0xFFFFFFFFu)
+                    KS[sub_hist[sbk[e]] + fp[e]] = ((key[e] >> 21) << 32) | sid[e];
+            __syncthreads();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                if (!((tie >> e) & 1u))
-                    continue;
-                uint64_t km = 0;
-                uint32_t so = 0, run = 0;
-                if (fused) {
-                    // equal top bits: the whole keys (same cell, so the
-                    // same run) decide, then the ids
-                    const int cl = gcl[e];
-                    so = a.seg_off ? g_seg[cl] : 0u;
-                    run = g_run[cl];
-                    km = philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
+                const uint32_t sb = sbk[e] != 0xFFFFFFFFu ? sbk[e] : 0u;
+                rlo[e] = sub_hist[sb];
+                rhi[e] = sbk[e] != 0xFFFFFFFFu ? sub_hist[sb + 1] : rlo[e];
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t hm = (uint32_t)(key[e] >> 21);
+                uint32_t r = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < RW; ++j) {
+                    const uint64_t w = KS[min(rlo[e] + j, (uint32_t)CAP - 1u)];
+                    const uint32_t hq = (uint32_t)(w >> 32);
+                    const bool in = rlo[e] + j < rhi[e];
+                    r += in && hq < hm;
+                    if (in && hq == hm && (uint32_t)w != sid[e])
+                        tie |= 1u << e;
                 }
-                for (uint32_t q = rlo[e]; q < rhi[e]; ++q) {
-                    const uint32_t sq = S1[q];
-                    if (K1[q] != key[e] || sq == sid[e])
+                for (uint32_t q = rlo[e] + RW; q < rhi[e]; ++q) {
+                    const uint64_t w = KS[q];
+                    const uint32_t hq = (uint32_t)(w >> 32);
+                    r += hq < hm;
+                    if (hq == hm && (uint32_t)w != sid[e])
+                        tie |= 1u << e;
+                }
+                fp[e] = rlo[e] + r;
+            }
+            if (tie) {
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    if (!((tie >> e) & 1u))
                         continue;
-                    if (fused) {
+                    // equal top bits: the whole keys (same cell, so the same
+                    // run) decide, then the ids
+                    const int cl = gcl[e];
+                    const uint32_t so = a.seg_off ? g_seg[cl] : 0u;
+                    const uint32_t run = g_run[cl];
+                    const uint32_t hm = (uint32_t)(key[e] >> 21);
+                    const uint64_t km =
+                        philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
+                    for (uint32_t q = rlo[e]; q < rhi[e]; ++q) {
+                        const uint64_t w = KS[q];
+                        const uint32_t sq = (uint32_t)w;
+                        if ((uint32_t)(w >> 32) != hm || sq == sid[e])
+                            continue;
                         const uint64_t kx =
                             philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sq - so) >> 11;
                         fp[e] += (kx < km) || (kx == km && sq < sid[e]);
-                    } else {
-                        fp[e] += sq < sid[e];
                     }
                 }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                if (sbk[e] != 0xFFFFFFFFu) {
+                    const uint32_t pos = sub_hist[sbk[e]] + fp[e];
+                    K1[pos] = key[e];
+                    S1[pos] = sid[e];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t sb = sbk[e] != 0xFFFFFFFFu ? sbk[e] : 0u;
+                rlo[e] = sub_hist[sb];
+                rhi[e] = sbk[e] != 0xFFFFFFFFu ? sub_hist[sb + 1] : rlo[e];
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                uint32_t r = 0;
+                for (uint32_t q = rlo[e]; q < rhi[e]; ++q) {
+                    const uint64_t kq = K1[q];
+                    r += (kq < key[e]) || (kq == key[e] && S1[q] < sid[e]);
+                }
+                fp[e] = rlo[e] + r;
             }
         }
         __syncthreads();  // keys and ids are dead
@@ -1223,8 +1258,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 if (!valid[u])
                     continue;
                 const uint32_t f = fv[u];
-                finish_pair(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[f], RX[f], RS[f + 1],
-                            RX[f + 1], st);
+                finish_pair_v(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[f], RX[f], RV[f],
+                              RS[f + 1], RX[f + 1], RV[f + 1], st);
             }
         }
         if (a.counters)
