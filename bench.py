@@ -23,12 +23,14 @@ Workloads (--workload, default box):
              (features, hull test, bf16 MFMA forward, moment update), beside
              one SDM step of the same grid (cell-steps/s of both).
 
-W warm-up steps run first; then exactly K steps are timed on one stream,
-bracketed by synchronisation; the library records HIP events between its
-kernels on that stream, which give the per-kernel durations for the roofline
-of the dominant kernel.  The same K steps are also captured in a HIP graph
-and replayed once (graph_ms_per_step).  The oracle (plain C, one host
-thread) is timed on a bounded sample of the same workload (cpu_baseline).
+W warm-up steps run first.  Then K steps are captured in one HIP graph,
+replayed once untimed and once timed, bracketed by synchronisation: that
+replay gives value and ms_per_step (--eager: the eager pass below instead).
+A separate eager pass of K steps on one stream, where the library records
+HIP events between its kernels, gives the per-kernel durations for the
+roofline of the dominant kernel (eager_ms_per_step is that pass's wall
+time).  The oracle (plain C, one host thread) is timed on a bounded sample
+of the same workload (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -112,6 +114,10 @@ class HipEvent:
 
 # Step kernels between the library's four event marks.
 INTERVALS = ("k_tile+k_scan", "k_group", "k_finish")
+# how the headline is timed (--eager: the event-marked eager pass instead)
+TIMING = ("K steps replayed from one captured HIP graph (value, ms_per_step); per-kernel "
+          "durations from a separate eager pass of K steps with HIP events")
+TIMING_EAGER = "K eager steps on one stream, HIP events between the kernels"
 
 
 def algorithmic_bytes(pairs, f_coll, per_pair_read, per_pair_write_idx, per_pair_coll):
@@ -218,17 +224,19 @@ def bench_box(args, sdm, torch, np, workloads):
     # collision (32 B): 48 + 32 f_coll
     ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
     workload = "golovin_box_2_%d" % args.log2_n_sd
+    step_ms = gms if gms else total_ms / K
     out = base_line("SDM pair-steps/s at n_sd=2^%d" % args.log2_n_sd,
-                    (n_sd // 2) * K / (total_ms / 1e3), "pair-steps/s", K, args.warmup,
-                    total_ms / K, "f64",
+                    (n_sd // 2) / (step_ms / 1e3), "pair-steps/s", K, args.warmup,
+                    step_ms, "f64",
                     {"workload": workload, "n_sd": n_sd, "cells": 1, "kernel": "golovin",
                      "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 2,
-                     "timing": "eager, one stream, HIP events per kernel",
+                     "timing": TIMING if gms else TIMING_EAGER,
                      "n_live": int(st.n_live.item()), "collision_fraction": f_coll})
     out["roofline"] = roofline(ab, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
-    step_gbs = ab["step"] / (total_ms / K / 1e3) / 1e9
+    out["eager_ms_per_step"] = total_ms / K
+    step_gbs = ab["step"] / (step_ms / 1e3) / 1e9
     out["step_roofline"] = {"bound": "hbm", "bytes_per_step": ab["step"], "achieved": step_gbs,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": step_gbs / HBM_PEAK_GBS}
@@ -285,16 +293,18 @@ def bench_grid(args, sdm, torch, np, workloads):
     # attributes of two SDs written back on a collision (48 B): 72 + 48 f_coll
     ab = algorithmic_bytes(pairs, f_coll, 64.0, 8.0, 48.0)
     workload = "grid_128x128"
-    out = base_line("SDM pair-steps/s on the 128x128 grid", pairs * K / (total_ms / 1e3),
-                    "pair-steps/s", K, args.warmup, total_ms / K, "f64",
+    step_ms = gms if gms else total_ms / K
+    out = base_line("SDM pair-steps/s on the 128x128 grid", pairs / (step_ms / 1e3),
+                    "pair-steps/s", K, args.warmup, step_ms, "f64",
                     {"workload": workload, "n_sd": n_sd, "cells": n_cell, "kernel": "geometric",
                      "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 3,
                      "reassignment": "every step, inside the timed region",
-                     "pairs_per_step": pairs, "collision_fraction": f_coll})
-    out["cell_steps_per_s"] = n_cell * K / (total_ms / 1e3)
+                     "pairs_per_step": pairs, "collision_fraction": f_coll, "timing": TIMING if gms else TIMING_EAGER})
+    out["cell_steps_per_s"] = n_cell / (step_ms / 1e3)
     out["roofline"] = roofline(ab, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
+    out["eager_ms_per_step"] = total_ms / K
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         import oracle
@@ -345,15 +355,17 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     assert ctx.read_errors() == 0
     ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
     workload = "ensemble_1024"
-    out = base_line("SDM pair-steps/s, 1024-run batched ensemble", pairs * K / (total_ms / 1e3),
-                    "pair-steps/s", K, args.warmup, total_ms / K, "f64",
+    step_ms = gms if gms else total_ms / K
+    out = base_line("SDM pair-steps/s, 1024-run batched ensemble", pairs / (step_ms / 1e3),
+                    "pair-steps/s", K, args.warmup, step_ms, "f64",
                     {"workload": workload, "runs": len(segs), "n_sd": int(sum(s[1] for s in segs)),
                      "kernels": "golovin (even runs), geometric (odd runs)", "dt_s": ens["dt"],
                      "seed": 4, "schedule": chosen, "pairs_per_step": pairs,
-                     "collision_fraction": f_coll})
+                     "collision_fraction": f_coll, "timing": TIMING if gms else TIMING_EAGER})
     out["roofline"] = roofline(ab, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
+    out["eager_ms_per_step"] = total_ms / K
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         import oracle

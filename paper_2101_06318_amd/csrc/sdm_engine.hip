@@ -363,7 +363,13 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     const int64_t n_items = LIST ? *a.n_live_in : a.n_sd;
     const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
 
-    uint64_t key[EPT];
+    // list modes keep whole keys; the fused mode keeps the top 32 bits and,
+    // with up to 8 slots per thread (registers allow it), loads the volumes
+    // together with xi
+    constexpr bool EARLY_V = !LIST && EPT <= 8;
+    uint64_t key[LIST ? EPT : 1];
+    uint32_t k32[LIST ? 1 : EPT];
+    double vv[LIST ? 1 : EPT];
     uint64_t xv[EPT];
     uint32_t bk[EPT];  // bucket (low 16 bits) | rank in tile (high 16 bits)
     uint32_t sid[LIST ? EPT : 1];
@@ -379,12 +385,24 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         if (!LIST) {
             s[0] = (uint32_t)i0;
             s[1] = (uint32_t)(i0 + 1);
+            double v[2] = {0.0, 0.0};
             if (i0 + 1 < n_items) {
                 const ulonglong2 xx = *reinterpret_cast<const ulonglong2 *>(a.xi + i0);
                 x[0] = xx.x;
                 x[1] = xx.y;
+                if (EARLY_V) {
+                    const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
+                    v[0] = v2.x;
+                    v[1] = v2.y;
+                }
             } else if (i0 < n_items) {
                 x[0] = a.xi[i0];
+                if (EARLY_V)
+                    v[0] = a.v[i0];
+            }
+            if (EARLY_V) {
+                vv[2 * k] = v[0];
+                vv[2 * k + 1] = v[1];
             }
             live[0] = x[0] > 0;
             live[1] = x[1] > 0;
@@ -447,7 +465,10 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int j = 2 * k + e;
-            key[j] = kk[e];
+            if (LIST)
+                key[j] = kk[e];
+            else
+                k32[j] = (uint32_t)(kk[e] >> 21);
             xv[j] = x[e];
             if (LIST)
                 sid[j] = s[e];
@@ -532,30 +553,31 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                 sts[pos[j] - c0] =
                     (uint64_t)(uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
                                          (j & 1)) |
-                    ((key[j] >> 21) << 32);
+                    ((uint64_t)k32[j] << 32);
         __syncthreads();
         const uint32_t n = min(CHS, total - c0);
         for (uint32_t i = tid; i < n; i += THREADS)
             a.rec_sk[rbase + c0 + i] = sts[i];
         __syncthreads();
     }
-    // volumes, read now as coalesced pairs (the keys are dead)
-    double vv[EPT];
+    if (!EARLY_V) {
+        // volumes, read now as coalesced pairs (the keys are dead)
 #pragma unroll
-    for (int k = 0; k < EPT / 2; ++k) {
-        const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
-        double v0 = 0.0, v1 = 0.0;
-        if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
-            if (i0 + 1 < n_items) {
-                const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
-                v0 = v2.x;
-                v1 = v2.y;
-            } else {
-                v0 = a.v[i0];
+        for (int k = 0; k < EPT / 2; ++k) {
+            const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
+            double v0 = 0.0, v1 = 0.0;
+            if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
+                if (i0 + 1 < n_items) {
+                    const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
+                    v0 = v2.x;
+                    v1 = v2.y;
+                } else {
+                    v0 = a.v[i0];
+                }
             }
+            vv[2 * k] = v0;
+            vv[2 * k + 1] = v1;
         }
-        vv[2 * k] = v0;
-        vv[2 * k + 1] = v1;
     }
     RecX *stx = reinterpret_cast<RecX *>(stage);
     for (uint32_t c0 = 0; c0 < total; c0 += CH) {
