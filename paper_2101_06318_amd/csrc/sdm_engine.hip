@@ -8,9 +8,10 @@
 //  k_tile    one workgroup per tile of T SD slots (coalesced reads of xi and
 //            v): Step 0 liveness (xi > 0), Philox shuffle key, bucket =
 //            (cell, top key bits); an LDS counting sort by bucket, then the
-//            tile's records (key, s, xi, v) are written contiguously through
-//            LDS staging, with the tile's per-bucket offsets.  No global
-//            atomics except one per tile (live total).
+//            tile's records (id with the key's top 32 bits, xi, v) are
+//            written contiguously through LDS staging, with the tile's
+//            per-bucket offsets.  No global atomics except one per tile
+//            (live total).
 //  k_colsum, k_bscan
 //            bucket totals (column sums of the tile offsets) and their
 //            exclusive scan: the global start rank of every bucket, hence of
@@ -18,7 +19,8 @@
 //  k_group   one workgroup per group of consecutive buckets: gathers the
 //            group's run from every tile, sorts in LDS (counting sort by the
 //            next key bits, then exact ranks by (key, s) in each
-//            sub-bucket), writes idx, and evaluates the pairs: probability,
+//            sub-bucket), keeps the sorted records in LDS, writes idx, and
+//            evaluates the pairs, two adjacent ones per thread: probability,
 //            gamma (one Philox block per two slots) and the collision update,
 //            written back only for pairs that collide.  Groups are
 //            independent; a pair straddling two groups leaves a seam record.
@@ -162,8 +164,6 @@ struct FinishArgs {
     const KernelDesc *kernels;
     uint64_t seed;
     uint32_t run;
-    uint32_t step;
-    const uint32_t *step_dev;
     int slot_cell_local;
     uint64_t *counters;
     double *gamma_out;
@@ -751,7 +751,7 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             rec.cell = a.bucket_cell[b0 + bl];
             rec.cs = cs;
             rec.n_c = T.n[bl];
-            rec.pad = 0;
+            rec.step = step;
             if (opener) {
                 a.seam_open[g] = rec;
                 state |= 1u;
@@ -1221,7 +1221,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 rec.cell = a.bucket_cell[b0 + bl];
                 rec.cs = cs;
                 rec.n_c = t_n[bl];
-                rec.pad = 0;
+                rec.step = step;
                 if (end) {
                     a.seam_open[g] = rec;
                     state |= 1u;
@@ -1350,53 +1350,59 @@ template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
 {
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];
-    __shared__ int s_last;
     const int g = blockIdx.x * THREADS + threadIdx.x;
-    const uint32_t step = step_of(a.step, a.step_dev);
     Stats st{0, 0, 0, 0, 0};
-    if (a.mode == MODE_FUSED && a.counters && g < a.G) {
-        const uint32_t *gs = a.group_stats + (int64_t)g * 5;
-        st.pairs = gs[0];
-        st.coll = gs[1];
-        st.capped = gs[2];
-        st.zeroed = gs[3];
-        st.ge2 = gs[4];
-    }
-    if (a.mode == MODE_FUSED && g < a.G && (a.seam_state[g] & 1u)) {
-        const SeamRec op = a.seam_open[g];
+    const bool fused = a.mode == MODE_FUSED;
+    if (fused && g < a.G) {
+        // the next group's records are read before knowing they are needed
+        // (one dependent round trip instead of three)
+        const uint32_t state = a.seam_state[g];
+        SeamRec op = a.seam_open[g];
         int g2 = g + 1;
-        while (g2 < a.G && a.group_tot[g2] == 0)
-            ++g2;
+        SeamRec cl;
+        uint32_t tot2 = 0;
         if (g2 < a.G) {
-            const SeamRec cl = a.seam_close[g2];
-            const PairCtx pc = pair_ctx(a, op.cell, op.cs, op.n_c);
-            const uint32_t q = (op.rank - pc.slot_base) >> 1;
-            const double p = pair_prob(pc, op.xi, op.v, cl.xi, cl.v);
-            const double phi =
-                word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
-            finish_pair(a, pc, q, p, phi, op.s, op.xi, cl.s, cl.xi, st);
+            cl = a.seam_close[g2];
+            tot2 = a.group_tot[g2];
+        }
+        if (a.counters) {
+            const uint32_t *gs = a.group_stats + (int64_t)g * 5;
+            st.pairs = gs[0];
+            st.coll = gs[1];
+            st.capped = gs[2];
+            st.zeroed = gs[3];
+            st.ge2 = gs[4];
+        }
+        if (state & 1u) {
+            if (g2 < a.G && tot2 == 0) {
+                while (g2 < a.G && a.group_tot[g2] == 0)
+                    ++g2;
+                if (g2 < a.G)
+                    cl = a.seam_close[g2];
+            }
+            if (g2 < a.G) {
+                // the step the group kernel drew its numbers for travels in
+                // the record, so that no block reads the step counter that
+                // block 0 advances
+                const uint32_t step = op.step;
+                const PairCtx pc = pair_ctx(a, op.cell, op.cs, op.n_c);
+                const uint32_t q = (op.rank - pc.slot_base) >> 1;
+                const double p = pair_prob(pc, op.xi, op.v, cl.xi, cl.v);
+                const double phi =
+                    word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
+                finish_pair_v(a, pc, q, p, phi, op.s, op.xi, op.v, cl.s, cl.xi, cl.v, st);
+            }
         }
     }
-    if (a.mode == MODE_FUSED && a.counters)
+    if (fused && a.counters)
         flush_stats<THREADS>(st, a.counters, red);
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) {
-            const uint32_t n = a.n_acc[0];
-            *a.n_live_out = (int64_t)n;
-            a.cell_start[a.n_cell] = n;
-            a.n_acc[0] = 0;
-        }
-    }
-    if (a.step_advance) {
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            s_last = atomicAdd(&a.n_acc[3], 1u) == gridDim.x - 1;
-        __syncthreads();
-        if (s_last && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t n = a.n_acc[0];
+        *a.n_live_out = (int64_t)n;
+        a.cell_start[a.n_cell] = n;
+        a.n_acc[0] = 0;
+        if (a.step_advance)
             *a.step_advance = *a.step_advance + 1u;
-            a.n_acc[3] = 0;
-        }
     }
 }
 
@@ -1841,8 +1847,6 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     fa.kernels = p->kernels;
     fa.seed = in.seed;
     fa.run = in.run;
-    fa.step = in.step;
-    fa.step_dev = in.step_dev;
     fa.slot_cell_local = in.slot_cell_local ? 1 : 0;
     fa.counters = in.counters;
     fa.gamma_out = in.gamma_out;

@@ -82,7 +82,7 @@ struct SeamRec {
     int32_t cell;
     uint32_t cs;   // rank of the cell's first SD
     uint32_t n_c;  // live SDs in the cell
-    uint32_t pad;
+    uint32_t step; // the step the group kernel drew its numbers for
 };
 
 // Bucketed sort plan.  The live SDs of cell c are split by the top h[c]
