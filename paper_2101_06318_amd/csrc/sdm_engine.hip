@@ -357,11 +357,43 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     const int tid = threadIdx.x;
     for (int i = tid; i <= B; i += THREADS)
         hist[i] = 0;
-    __syncthreads();
 
     const uint32_t step = step_of(a.step, a.step_dev);
     const int64_t n_items = LIST ? *a.n_live_in : a.n_sd;
     const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
+
+    // batched runs (fused mode): the runs this tile's slots fall in, with
+    // their offset, length, Philox run, key bits and first bucket, in LDS
+    // (up to SEGTAB runs; more fall back to global lookups)
+    constexpr int SEGTAB = 256;
+    __shared__ uint32_t st_off[SEGTAB + 1];
+    __shared__ uint32_t st_len[SEGTAB];
+    __shared__ int32_t st_run[SEGTAB], st_h[SEGTAB], st_bb[SEGTAB];
+    __shared__ int st_first, st_n;
+    const bool segtab = !LIST && a.seg_off != nullptr;
+    if (segtab) {
+        if (tid == 0) {
+            const int64_t last = n_items > 0 ? n_items - 1 : 0;
+            const uint32_t s_lo = (uint32_t)min<int64_t>(2 * pair0, last);
+            const uint32_t s_hi = (uint32_t)min<int64_t>(2 * pair0 + T - 1, last);
+            const int f = find_seg(a.seg_off, a.n_cell, s_lo);
+            const int l = find_seg(a.seg_off, a.n_cell, s_hi);
+            st_first = f;
+            st_n = l - f + 1 <= SEGTAB ? l - f + 1 : 0;
+        }
+        __syncthreads();
+        const int f = st_first, n = st_n;
+        for (int i = tid; i < n; i += THREADS) {
+            st_off[i] = a.seg_off[f + i];
+            st_len[i] = a.seg_len[f + i];
+            st_run[i] = a.seg_run[f + i];
+            st_h[i] = a.cell_h[f + i];
+            st_bb[i] = a.cell_bucket_base[f + i];
+        }
+        if (tid == 0 && n > 0)
+            st_off[n] = a.seg_off[f + n];
+    }
+    __syncthreads();
 
     // list modes keep whole keys; the fused mode keeps the top 32 bits and,
     // with up to 8 slots per thread (registers allow it), loads the volumes
@@ -373,6 +405,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     uint64_t xv[EPT];
     uint32_t bk[EPT];  // bucket (low 16 bits) | rank in tile (high 16 bits)
     uint32_t sid[LIST ? EPT : 1];
+    const int seg_n = segtab ? st_n : 0;
 
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
@@ -413,7 +446,18 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             s[1] = live[1] ? a.idx_in[i0 + 1] : 0;
         }
         int seg = 0;
-        if (a.seg_off) {
+        int ti = -1;  // the run's row in the LDS table
+        if (seg_n > 0) {
+            // the two slots of a pair share a run (runs start at even slots);
+            // slots past a run's length (alignment padding) belong to none
+            ti = upper_index(st_off, seg_n, s[0]);
+            seg = st_first + ti;
+            cell[0] = cell[1] = seg;
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (s[e] - st_off[ti] >= st_len[ti])
+                    live[e] = false;
+        } else if (a.seg_off) {
             // batched runs: slots past a run's length (alignment padding)
             // belong to no run
             seg = find_seg(a.seg_off, a.n_cell, s[0]);
@@ -448,7 +492,10 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             if (live[0] || live[1]) {
                 uint32_t run = a.run;
                 uint64_t lp = (uint64_t)p;
-                if (a.seg_off) {
+                if (ti >= 0) {
+                    run = (uint32_t)st_run[ti];
+                    lp = (uint64_t)p - (st_off[ti] >> 1);
+                } else if (a.seg_off) {
                     run = (uint32_t)a.seg_run[seg];
                     lp = (uint64_t)p - (a.seg_off[seg] >> 1);
                 }
@@ -474,9 +521,10 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                 sid[j] = s[e];
             bk[j] = NO_BUCKET;
             if (live[e]) {
-                const int h = a.cell_h[cell[e]];
-                const uint32_t b = (uint32_t)a.cell_bucket_base[cell[e]] +
-                                   (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
+                const int h = ti >= 0 ? st_h[ti] : a.cell_h[cell[e]];
+                const uint32_t bb =
+                    (uint32_t)(ti >= 0 ? st_bb[ti] : a.cell_bucket_base[cell[e]]);
+                const uint32_t b = bb + (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
                 const uint32_t r = atomicAdd(&hist[b], 1u);
                 bk[j] = b | (r << 16);
             }
