@@ -249,7 +249,7 @@ typedef struct {
                                      /* and after it, for timing            */
 } sdm_step_params;
 
-/* One whole timestep (workflow figure, Steps 0-3) in five kernels, with the
+/* One whole timestep (workflow figure, Steps 0-3) in four kernels, with the
  * result of running the routines above in the paper's order with inline
  * random numbers: the live set is {s : xi[s] > 0} (Step 0), idx receives
  * the live SDs sorted by (cell, shuffle key, s), the pairs and slots are
@@ -283,7 +283,7 @@ int sdm_batch_create(sdm_ctx *ctx, sdm_batch **b, const sdm_segment *segs,
                      int32_t n_seg);
 int sdm_batch_destroy(sdm_ctx *ctx, sdm_batch *b);
 
-/* One timestep of every run of the batch in one five-kernel launch
+/* One timestep of every run of the batch in one four-kernel launch
  * sequence (graph-capturable after the first call).  st->n_cell must equal
  * the number of segments and st->cell_id is ignored; cell_start[r] receives
  * the first rank of run r, idx the sorted live SDs of every run (global SD

@@ -3,7 +3,7 @@
 // Step 1 of the paper (Sec. 2.2, Sec. 3.2) orders each cell's live SDs by a
 // random key (the GPU strategy the paper describes: a sort with random
 // keys) and pairs neighbours; Steps 2-3 evaluate eq. (3), gamma and
-// eqs. (4)-(6) per pair.  Five kernels:
+// eqs. (4)-(6) per pair.  Four kernels:
 //
 //  k_tile    one workgroup per tile of T SD slots (coalesced reads of xi and
 //            v): Step 0 liveness (xi > 0), Philox shuffle key, bucket =
@@ -12,10 +12,9 @@
 //            written contiguously through LDS staging, with the tile's
 //            per-bucket offsets.  No global atomics except one per tile
 //            (live total).
-//  k_colsum, k_bscan
-//            bucket totals (column sums of the tile offsets) and their
-//            exclusive scan: the global start rank of every bucket, hence of
-//            every group and cell.
+//  k_colsum  the global start rank of every bucket (hence of every group
+//            and cell): the column sums of the tiles' exclusive bucket
+//            offsets; and those offsets transposed to bucket-major order.
 //  k_group   one workgroup per group of consecutive buckets: gathers the
 //            group's run from every tile, sorts in LDS (counting sort by the
 //            next key bits, then exact ranks by (key, s) in each
@@ -86,6 +85,7 @@ struct TileArgs {
     uint64_t *rec_sk;      // fused mode: id | (key >> 21) << 32
     RecX *rec_x;           // fused mode: (xi, v)
     uint32_t chunk;        // 16-B records per LDS staging pass
+    uint32_t *start_zero;  // bucket_start to clear for k_colsum's sums (or null)
     uint32_t *n_acc;
     uint32_t *err;
 };
@@ -275,72 +275,58 @@ __device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_
     __syncthreads();
 }
 
-// ---------------------------------------------------------------- k_scan
-// Global start rank of every bucket.  k_colsum: bucket totals, the column
-// sums of the tiles' bucket offsets (one wave per bucket), and the offsets
-// transposed to bucket-major order for the groups; k_bscan: their
-// exclusive scan in one workgroup.  Two launches instead of a last-block
-// handshake: no device-scope fence right after the tile kernel's writes.
+// -------------------------------------------------------------- k_colsum
 struct ScanArgs {
     const uint16_t *tile_off;
     uint16_t *tile_offT;     // [B+1][n_tiles] transposed copy for the groups
     int32_t n_tiles;
     int32_t B;
-    uint32_t *bucket_tot;    // [B]
     uint32_t *bucket_start;  // [B+1]
 };
 
+// Global start rank of every bucket: bucket b starts after the records of
+// buckets < b in every tile, i.e. at the sum over tiles of the tile's
+// exclusive offset of b (column sums of tile_off; column B gives the live
+// total).  One workgroup per 64 x 64 block of (tiles, buckets): coalesced
+// row reads, the block transposed through LDS into tile_offT, partial column
+// sums added into bucket_start (zeroed by the tile kernel when the tiles
+// span more than one block).
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
 {
     constexpr int W = THREADS / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int b = blockIdx.x * W + wid;
-    if (b > a.B)
-        return;
+    __shared__ uint16_t blk[64][66];  // [tile][bucket], rows padded against bank conflicts
+    __shared__ uint32_t part[W][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
     const int64_t Bp = a.B + 1;
+    const int c = c0 + lane;
     uint32_t sum = 0;
-    for (int t = lane; t < a.n_tiles; t += 64) {
-        const uint16_t lo = a.tile_off[t * Bp + b];
-        a.tile_offT[(int64_t)b * a.n_tiles + t] = lo;
-        if (b < a.B)
-            sum += (uint32_t)a.tile_off[t * Bp + b + 1] - (uint32_t)lo;
+    for (int i = w; i < 64; i += W) {
+        const int t = t0 + i;
+        uint16_t v = 0;
+        if (t < a.n_tiles && c <= a.B)
+            v = a.tile_off[t * Bp + c];
+        blk[i][lane] = v;
+        sum += v;
     }
-    if (b == a.B)
-        return;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        sum += __shfl_xor(sum, o, 64);
-    if (lane == 0)
-        a.bucket_tot[b] = sum;
-}
-
-template <int THREADS, int PER>
-__global__ __launch_bounds__(THREADS) void k_bscan(ScanArgs a)
-{
-    __shared__ uint32_t buf[THREADS * PER];  // totals, then starts (coalesced in and out)
-    __shared__ uint32_t red[THREADS / 64 + 1];
-    for (int i = threadIdx.x; i < THREADS * PER; i += THREADS)
-        buf[i] = i < a.B ? a.bucket_tot[i] : 0u;
+    part[w][lane] = sum;
     __syncthreads();
-    const int i0 = (int)threadIdx.x * PER;
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-        sum += buf[i0 + i];
-    uint32_t total;
-    uint32_t run = block_exclusive_scan<THREADS>(sum, red, &total);
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const uint32_t v = buf[i0 + i];
-        buf[i0 + i] = run;
-        run += v;
+    for (int j = w; j < 64; j += W) {
+        const int cc = c0 + j, t = t0 + lane;
+        if (cc <= a.B && t < a.n_tiles)
+            a.tile_offT[(int64_t)cc * a.n_tiles + t] = blk[lane][j];
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < a.B; i += THREADS)
-        a.bucket_start[i] = buf[i];
-    if (threadIdx.x == 0)
-        a.bucket_start[a.B] = total;
+    if (w == 0 && c <= a.B) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+            s += part[i][lane];
+        if (gridDim.y == 1)
+            a.bucket_start[c] = s;
+        else
+            atomicAdd(&a.bucket_start[c], s);
+    }
 }
 
 // ---------------------------------------------------------------- k_tile
@@ -357,6 +343,9 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     const int tid = threadIdx.x;
     for (int i = tid; i <= B; i += THREADS)
         hist[i] = 0;
+    if (a.start_zero)
+        for (int i = blockIdx.x * THREADS + tid; i <= B; i += gridDim.x * THREADS)
+            a.start_zero[i] = 0;
 
     const uint32_t step = step_of(a.step, a.step_dev);
     const int64_t n_items = LIST ? *a.n_live_in : a.n_sd;
@@ -1640,7 +1629,6 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
         }
         p->n_acc = (uint32_t *)dalloc(p, 64);
-        p->bucket_tot = (uint32_t *)dalloc(p, 4ull * B);
         p->bucket_start = (uint32_t *)dalloc(p, 4ull * (B + 1));
         p->cell_start_ws = (uint32_t *)dalloc(p, 4ull * (C + 1));
         p->n_live_ws = (int64_t *)dalloc(p, 8);
@@ -1790,6 +1778,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.rec_sk = p->rec_sk;
     ta.rec_x = p->rec_x;
     ta.chunk = p->chunk;
+    ta.start_zero = p->n_tiles > 64 ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
     const size_t lds = (size_t)tile_hist_bytes(p->B) + (size_t)p->chunk * sizeof(RecK);
@@ -1805,12 +1794,9 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
         sa.tile_offT = p->tile_offT;
         sa.n_tiles = p->n_tiles;
         sa.B = p->B;
-        sa.bucket_tot = p->bucket_tot;
         sa.bucket_start = p->bucket_start;
-        constexpr int ST = 256;
-        hipLaunchKernelGGL((k_colsum<ST>), dim3((p->B + 1 + ST / 64 - 1) / (ST / 64)), dim3(ST),
-                           0, stream, sa);
-        hipLaunchKernelGGL((k_bscan<1024, MAX_B / 1024>), dim3(1), dim3(1024), 0, stream, sa);
+        hipLaunchKernelGGL((k_colsum<256>), dim3((p->B + 1 + 63) / 64, (p->n_tiles + 63) / 64),
+                           dim3(256), 0, stream, sa);
         SDM_HIP(hipGetLastError());
     }
 

@@ -122,7 +122,6 @@ struct Plan {
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     int gept = 0;                         // records per group-kernel thread (4 or 8)
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
-    uint32_t *bucket_tot = nullptr;       // [B] live SDs per bucket
     uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
     uint32_t *cell_start_ws = nullptr;    // [C+1]
     int64_t *n_live_ws = nullptr;         // [1]

@@ -1,7 +1,7 @@
 // The backend API routines of the timestep workflow (arXiv:2101.06318,
 // Sec. 3.2), one HIP kernel each, behind the C ABI of include/sdm.h.  These
 // are the building blocks a caller composes step by step; the fused
-// timestep (sdm_step) computes the same result in five kernels.
+// timestep (sdm_step) computes the same result in four kernels.
 #include <math.h>
 
 #include <algorithm>
