@@ -1595,14 +1595,11 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             group_first.push_back(B);
         }
         // the largest tile that still gives every CU a tile (longer runs for
-        // the groups), at least 4 slots per thread; a tile's bucket table
-        // (scan, offsets) costs in proportion to B, so smaller tiles only
-        // while B stays well below the tile size
+        // the groups), at least 4 slots per thread
         int ept = TILE_EPT_MAX;
         while (ept > 4 &&
                (n_items + (int64_t)TILE_THREADS * ept - 1) / ((int64_t)TILE_THREADS * ept) <
-                   TILE_FILL &&
-               2 * (int64_t)B <= (int64_t)TILE_THREADS * (ept / 2))
+                   TILE_FILL)
             ept /= 2;
         p->tile = TILE_THREADS * ept;
         p->chunk = tile_chunk_for(B, p->tile);
