@@ -246,17 +246,20 @@ def bench_box(args, sdm, torch, np, workloads):
         n = n_sd
         s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
         t0 = time.perf_counter()
-        for t in range(args.cpu_steps):
+        npairs = steps = 0
+        while time.perf_counter() - t0 < args.cpu_seconds:
             s = oracle.step(s["xi"], s["attr"], None, 1, w["dv"], s["idx"], s["n_live"],
                             dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
-                            seed=2, run=0, step=t)
+                            seed=2, run=0, step=steps)
+            npairs += int(s["counters"][oracle.CNT_PAIRS])
+            steps += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {
-            "value": (n // 2) * args.cpu_steps / dt, "unit": "pair-steps/s", "cores": 1,
+            "value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
             "kind": "oracle", "seconds": round(dt, 3),
-            "sample": "%d steps of the 2^%d-SD Golovin box (seed 2) from its initial state, "
-                      "oracle (plain C, one thread, qsort-based shuffle)"
-                      % (args.cpu_steps, args.log2_n_sd)}
+            "sample": "the first %d steps of the 2^%d-SD Golovin box (seed 2) from its initial "
+                      "state, oracle (plain C, one thread, qsort-based shuffle)"
+                      % (steps, args.log2_n_sd)}
     ctx.close()
     return out
 
@@ -309,15 +312,15 @@ def bench_grid(args, sdm, torch, np, workloads):
     if not args.no_cpu_baseline:
         import oracle
         s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
-        steps = max(1, args.cpu_steps // 2)
         t0 = time.perf_counter()
-        npairs = 0
-        for t in range(steps):
-            cid = oracle.reassign(n_sd, n_cell, 3, t)
+        npairs = steps = 0
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            cid = oracle.reassign(n_sd, n_cell, 3, steps)
             s = oracle.step(s["xi"], s["attr"], cid, n_cell, w["dv"], s["idx"], s["n_live"],
                             dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"], seed=3,
-                            run=0, step=t)
+                            run=0, step=steps)
             npairs += int(s["counters"][oracle.CNT_PAIRS])
+            steps += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
                                "kind": "oracle", "seconds": round(dt, 3),
@@ -370,19 +373,21 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.perf_counter()
-        npairs = 0
-        members = ens["runs"][:128]
-        for m in members:
+        npairs = done = 0
+        for m in ens["runs"]:
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
             s = oracle.step(m["xi"], m["attr"], None, 1, [m["dv"]],
                             np.arange(m["n_sd"], dtype=np.uint32), m["n_sd"], dt=ens["dt"],
                             kernel_id=m["kernel_id"], kparams=m["kparams"], seed=4,
                             run=m["run"], step=0)
             npairs += int(s["counters"][oracle.CNT_PAIRS])
+            done += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
                                "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "one step of the first 128 of the 1024 runs, "
-                                         "oracle (plain C, one thread)"}
+                               "sample": "one step of each of the first %d of the 1024 runs, "
+                                         "oracle (plain C, one thread)" % done}
     b.close()
     ctx.close()
     return out
@@ -457,14 +462,16 @@ def bench_golovin(args, sdm, torch, np, workloads):
     if not args.no_cpu_baseline:
         import oracle
         s_ = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
-        steps = 600
         t0 = time.perf_counter()
-        for t in range(steps):
+        npairs = steps = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and steps < 3600:
             s_ = oracle.step(s_["xi"], s_["attr"], None, 1, w["dv"], s_["idx"], s_["n_live"],
                              dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
-                             seed=1, run=0, step=t)
+                             seed=1, run=0, step=steps)
+            npairs += int(s_["counters"][oracle.CNT_PAIRS])
+            steps += 1
         dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": (n_sd // 2) * steps / dt, "unit": "pair-steps/s",
+        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s",
                                "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
                                "sample": "the first %d of the 3600 steps, oracle (plain C, one "
                                          "thread)" % steps}
@@ -537,31 +544,37 @@ def bench_surrogate(args, sdm, torch, np, workloads):
 
     for t in range(args.warmup):
         sdm_step(t, None, None)
-    sdm_ms, _, _ = timed_steps(sdm, torch, sdm_step, K, lib)
+    sdm_ms, _, sdm_stream = timed_steps(sdm, torch, sdm_step, K, lib)
+    sdm_gms = None if args.eager else graph_ms(torch, sdm_step, K, sdm_stream)
     flop = MLP_FLOP_PER_SAMPLE * n_cell
     achieved = flop / (fwd_ms / 1e3) / 1e12
-    out = base_line("surrogate cell-steps/s on the 128x128 grid", n_cell * K / (sur_ms / 1e3),
-                    "cell-steps/s", K, args.warmup, sur_ms / K, "bf16",
+    step_ms = gms if gms else sur_ms / K
+    sdm_step_ms = sdm_gms if (gms and sdm_gms) else sdm_ms / K
+    out = base_line("surrogate cell-steps/s on the 128x128 grid", n_cell / (step_ms / 1e3),
+                    "cell-steps/s", K, args.warmup, step_ms, "bf16",
                     {"workload": "surrogate_grid_128x128", "cells": n_cell,
                      "network": "5-128-128-128-3 GELU", "dt_s": w["dt"], "seed": 3,
-                     "step": "features + hull test + forward + moment update"})
-    out["sdm_cell_steps_per_s"] = n_cell * K / (sdm_ms / 1e3)
+                     "step": "features + hull test + forward + moment update",
+                     "timing": TIMING if gms else TIMING_EAGER})
+    out["sdm_cell_steps_per_s"] = n_cell / (sdm_step_ms / 1e3)
     out["speedup_vs_sdm"] = out["value"] / out["sdm_cell_steps_per_s"]
     out["roofline"] = {"bound": "mfma", "kernel": "k_mlp_forward", "achieved": achieved,
                        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None}
     out["kernel_ms"] = {"k_mlp_forward": fwd_ms}
     out["graph_ms_per_step"] = gms
+    out["eager_ms_per_step"] = sur_ms / K
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         from oracle import mlp
         xh = x.cpu().numpy()
         th = workloads.mlp_init(7)
         net_o = mlp.Net("bf16")
-        reps = 3
+        reps = 0
         t0 = time.perf_counter()
-        for _ in range(reps):
+        while time.perf_counter() - t0 < args.cpu_seconds:
             net_o.forward(th, xh)
+            reps += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n_cell * reps / dt, "unit": "cell-steps/s",
                                "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
@@ -579,7 +592,8 @@ def main():
     ap.add_argument("--workload", default="box",
                     choices=["box", "grid", "ensemble", "golovin", "surrogate"])
     ap.add_argument("--log2-n-sd", type=int, default=22)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="host time given to the oracle baseline (whole steps, at least one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
     ap.add_argument("--calib-copy", action="store_true",
