@@ -215,7 +215,9 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
     return v;
 }
 
-// Exclusive scan over THREADS values held one per thread.
+// Exclusive scan over THREADS values held one per thread; *total gets the
+// sum.  One barrier: every wave adds up the wave totals before its own.  The
+// caller puts a barrier between the return and the next write to scratch.
 template <int THREADS>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *scratch,
                                                          uint32_t *total)
@@ -232,20 +234,15 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     if (lane == 63)
         scratch[wid] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < W; ++w) {
-            const uint32_t t = scratch[w];
-            scratch[w] = run;
-            run += t;
-        }
-        scratch[W] = run;
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t t = scratch[w];
+        before += w < wid ? t : 0u;
+        all += t;
     }
-    __syncthreads();
-    const uint32_t res = scratch[wid] + x - v;
-    *total = scratch[W];
-    __syncthreads();
-    return res;
+    *total = all;
+    return before + x - v;
 }
 
 // In-place exclusive scan of an LDS array of n <= THREADS*PER entries;
