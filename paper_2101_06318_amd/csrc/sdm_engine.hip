@@ -82,8 +82,7 @@ struct TileArgs {
     const int32_t *seg_run;
     uint16_t *tile_off;
     RecK *rec_k;           // list modes: (key, id)
-    uint64_t *rec_sk;      // fused mode: id | (key >> 21) << 32
-    RecX *rec_x;           // fused mode: (xi, v)
+    RecA *rec_a;           // fused mode records
     uint32_t chunk;        // 16-B records per LDS staging pass
     uint32_t *start_zero;  // bucket_start to clear for k_colsum's sums (or null)
     uint32_t *n_acc;
@@ -103,8 +102,7 @@ struct GroupArgs {
     const int32_t *cell_bucket_base;
     const uint16_t *tile_offT;  // [B+1][n_tiles]
     const RecK *rec_k;
-    const uint64_t *rec_sk;
-    const RecX *rec_x;
+    const RecA *rec_a;
     const int32_t *cell_id;
     const uint32_t *bucket_start;
     uint32_t *cell_start;
@@ -578,24 +576,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         }
         return;
     }
-    uint64_t *sts = stage;
-    const uint32_t CHS = 2 * CH;  // id words per pass
-    for (uint32_t c0 = 0; c0 < total; c0 += CHS) {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (pos[j] - c0 < CHS)
-                sts[pos[j] - c0] =
-                    (uint64_t)(uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
-                                         (j & 1)) |
-                    ((uint64_t)k32[j] << 32);
-        __syncthreads();
-        const uint32_t n = min(CHS, total - c0);
-        for (uint32_t i = tid; i < n; i += THREADS)
-            a.rec_sk[rbase + c0 + i] = sts[i];
-        __syncthreads();
-    }
     if (!EARLY_V) {
-        // volumes, read now as coalesced pairs (the keys are dead)
+        // volumes, read now as coalesced pairs
 #pragma unroll
         for (int k = 0; k < EPT / 2; ++k) {
             const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
@@ -613,23 +595,25 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             vv[2 * k + 1] = v1;
         }
     }
-    RecX *stx = reinterpret_cast<RecX *>(stage);
-    for (uint32_t c0 = 0; c0 < total; c0 += CH) {
+    uint64_t *sta = stage;
+    const uint32_t CHA = (2 * CH) / 3;  // 24-B records per pass
+    for (uint32_t c0 = 0; c0 < total; c0 += CHA) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            if (pos[j] - c0 < CH) {
-                RecX r;
-                r.xi = xv[j];
-                r.v = vv[j];
-                stx[pos[j] - c0] = r;
+            if (pos[j] - c0 < CHA) {
+                const uint32_t q = 3u * (pos[j] - c0);
+                sta[q] = (uint64_t)(uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
+                                              (j & 1)) |
+                         ((uint64_t)k32[j] << 32);
+                sta[q + 1] = xv[j];
+                sta[q + 2] = (uint64_t)__double_as_longlong(vv[j]);
             }
         }
         __syncthreads();
-        const uint32_t n = min(CH, total - c0);
-        const uint4 *src = reinterpret_cast<const uint4 *>(stx);
-        uint4 *dst = reinterpret_cast<uint4 *>(a.rec_x + rbase + c0);
-        for (uint32_t i = tid; i < n; i += THREADS)
-            dst[i] = src[i];
+        const uint32_t n3 = 3u * min(CHA, total - c0);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(a.rec_a + rbase + c0);
+        for (uint32_t i = tid; i < n3; i += THREADS)
+            dst[i] = sta[i];
         __syncthreads();
     }
 }
@@ -1055,12 +1039,11 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 const int t = tmap[li];
                 const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
                 if (fused) {
-                    const uint64_t sk = a.rec_sk[pos];
-                    sid[e] = (uint32_t)sk;
-                    key[e] = (sk >> 32) << 21;
-                    const RecX rx = a.rec_x[pos];
-                    xv[e] = rx.xi;
-                    vv[e] = rx.v;
+                    const RecA ra = a.rec_a[pos];
+                    sid[e] = (uint32_t)ra.sk;
+                    key[e] = (ra.sk >> 32) << 21;
+                    xv[e] = ra.xi;
+                    vv[e] = ra.v;
                 } else {
                     const RecK rk = a.rec_k[pos];
                     key[e] = rk.key;
@@ -1337,7 +1320,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, nt, li);
         const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
-        const uint32_t s = fused ? (uint32_t)a.rec_sk[pos] : a.rec_k[pos].s;
+        const uint32_t s = fused ? (uint32_t)a.rec_a[pos].sk : a.rec_k[pos].s;
         const uint64_t k =
             fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
         a.sk[base2 + li] = k;
@@ -1617,8 +1600,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         if (fused) {
-            p->rec_sk = (uint64_t *)dalloc(p, 8ull * R);
-            p->rec_x = (RecX *)dalloc(p, sizeof(RecX) * R);
+            p->rec_a = (RecA *)dalloc(p, sizeof(RecA) * R);
         } else {
             p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
         }
@@ -1769,8 +1751,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.seg_run = p->seg_run;
     ta.tile_off = p->tile_off;
     ta.rec_k = p->rec_k;
-    ta.rec_sk = p->rec_sk;
-    ta.rec_x = p->rec_x;
+    ta.rec_a = p->rec_a;
     ta.chunk = p->chunk;
     ta.start_zero = p->n_tiles > 64 ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
@@ -1807,8 +1788,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_bucket_base = p->cell_bucket_base;
     ga.tile_offT = p->tile_offT;
     ga.rec_k = p->rec_k;
-    ga.rec_sk = p->rec_sk;
-    ga.rec_x = p->rec_x;
+    ga.rec_a = p->rec_a;
     ga.cell_id = in.cell_id;
     ga.bucket_start = p->bucket_start;
     ga.cell_start = cell_start;

@@ -59,21 +59,23 @@ struct HipError {
 // ------------------------------------------------------------ engine plan
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
-// One SD's record between the tile and group kernels: (shuffle key, id) in
-// the list modes; id and (multiplicity, volume) in the fused step, whose
-// group kernel recomputes the key from the id.
+// One SD's record between the tile and group kernels.  List modes: (shuffle
+// key, id).  Fused step: id with the key's top 32 bits in the high word,
+// multiplicity and volume (24 B); the group kernel draws the whole key again
+// only for records whose top bits tie.
 struct __attribute__((aligned(16))) RecK {
     uint64_t key;
     uint32_t s;
     uint32_t pad;
 };
-struct __attribute__((aligned(16))) RecX {
+struct RecA {
+    uint64_t sk;
     uint64_t xi;
     double v;
 };
 
 // Pair that straddles two groups: the opener's record, written by the
-// group holding it and completed by the seam kernel.
+// group holding it and completed by the finish kernel.
 struct SeamRec {
     uint64_t xi;
     double v;
@@ -117,8 +119,7 @@ struct Plan {
     uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
     // records in tile-local bucket order, [n_tiles * tile]
     RecK *rec_k = nullptr;                // list modes: (key, id)
-    uint64_t *rec_sk = nullptr;           // fused mode: id | (key >> 21) << 32
-    RecX *rec_x = nullptr;                // fused mode: (xi, v)
+    RecA *rec_a = nullptr;                // fused mode records
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     int gept = 0;                         // records per group-kernel thread (4 or 8)
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
