@@ -596,7 +596,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         }
     }
     uint64_t *sta = stage;
-    const uint32_t CHA = (2 * CH) / 3;  // 24-B records per pass
+    // 24-B records per pass, even so that every pass starts 16-B aligned
+    const uint32_t CHA = ((2 * CH) / 3) & ~1u;
     for (uint32_t c0 = 0; c0 < total; c0 += CHA) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -612,8 +613,12 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         __syncthreads();
         const uint32_t n3 = 3u * min(CHA, total - c0);
         uint64_t *dst = reinterpret_cast<uint64_t *>(a.rec_a + rbase + c0);
-        for (uint32_t i = tid; i < n3; i += THREADS)
-            dst[i] = sta[i];
+        const uint4 *src4 = reinterpret_cast<const uint4 *>(sta);
+        uint4 *dst4 = reinterpret_cast<uint4 *>(dst);
+        for (uint32_t i = tid; i < n3 / 2; i += THREADS)
+            dst4[i] = src4[i];
+        if ((n3 & 1u) && tid == 0)
+            dst[n3 - 1] = sta[n3 - 1];
         __syncthreads();
     }
 }
