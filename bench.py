@@ -24,8 +24,9 @@ Workloads (--workload, default box):
              one SDM step of the same grid (cell-steps/s of both).
 
 W warm-up steps run first.  Then K steps are captured in one HIP graph,
-replayed once untimed and once timed, bracketed by synchronisation: that
-replay gives value and ms_per_step (--eager: the eager pass below instead).
+replayed once untimed and five times timed, each bracketed by
+synchronisation: the median replay gives value and ms_per_step (--eager:
+the eager pass below instead).
 A separate eager pass of K steps on one stream, where the library records
 HIP events between its kernels, gives the per-kernel durations for the
 roofline of the dominant kernel (eager_ms_per_step is that pass's wall
@@ -115,8 +116,9 @@ class HipEvent:
 # Step kernels between the library's four event marks.
 INTERVALS = ("k_tile+k_scan", "k_group", "k_finish")
 # how the headline is timed (--eager: the event-marked eager pass instead)
-TIMING = ("K steps replayed from one captured HIP graph (value, ms_per_step); per-kernel "
-          "durations from a separate eager pass of K steps with HIP events")
+GRAPH_REPLAYS = 5
+TIMING = ("K steps captured in one HIP graph, median of 5 timed replays (value, ms_per_step); "
+          "per-kernel durations from a separate eager pass of K steps with HIP events")
 TIMING_EAGER = "K eager steps on one stream, HIP events between the kernels"
 
 
@@ -166,15 +168,18 @@ def graph_ms(torch, run_step, K, stream):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        gs = torch.cuda.Event(enable_timing=True)
-        ge = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            gs.record(stream)
-            g.replay()
-            ge.record(stream)
-        torch.cuda.synchronize()
+        times = []
+        for _ in range(GRAPH_REPLAYS):
+            gs = torch.cuda.Event(enable_timing=True)
+            ge = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                gs.record(stream)
+                g.replay()
+                ge.record(stream)
+            torch.cuda.synchronize()
+            times.append(gs.elapsed_time(ge) / K)
         del g
-        return gs.elapsed_time(ge) / K
+        return sorted(times)[len(times) // 2]
     except Exception as e:  # reported, not fatal
         print("bench: graph replay not measured (%s)" % e, file=sys.stderr, flush=True)
         return None
