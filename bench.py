@@ -605,8 +605,8 @@ def main():
                     help="also run one plain 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the SDM step on one MI355X); "
-              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the SDM step runs and is measured on one MI355X only (no sharded "
+              "path); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

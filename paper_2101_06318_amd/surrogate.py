@@ -7,7 +7,7 @@ spectrum.  Here a network learns, per cell, the relative tendencies of the
 moments M_k = sum xi v^k / dV (k = 0, 1, 2) over one timestep from the
 cell's own moments, dt and the kernel; the particle method produces its
 training data, serves as its fallback outside the training inputs' box,
-and judges its error.  Every arithmetic step (particle steps, moments,
+and measures its error.  Every arithmetic step (particle steps, moments,
 features, hull test, forward, backward, loss, Adam, moment update) runs in
 the HIP library; torch holds device memory and draws minibatch orders.
 
