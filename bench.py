@@ -377,22 +377,25 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         import oracle
+        runs = ens["runs"]
+        states = [dict(xi=m["xi"], attr=m["attr"], idx=np.arange(m["n_sd"], dtype=np.uint32),
+                       n_live=m["n_sd"]) for m in runs]
         t0 = time.perf_counter()
         npairs = done = 0
-        for m in ens["runs"]:
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-            s = oracle.step(m["xi"], m["attr"], None, 1, [m["dv"]],
-                            np.arange(m["n_sd"], dtype=np.uint32), m["n_sd"], dt=ens["dt"],
-                            kernel_id=m["kernel_id"], kparams=m["kparams"], seed=4,
-                            run=m["run"], step=0)
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            r_ = done % len(runs)
+            m, s = runs[r_], states[r_]
+            s = oracle.step(s["xi"], s["attr"], None, 1, [m["dv"]], s["idx"], s["n_live"],
+                            dt=ens["dt"], kernel_id=m["kernel_id"], kparams=m["kparams"],
+                            seed=4, run=m["run"], step=done // len(runs))
+            states[r_] = s
             npairs += int(s["counters"][oracle.CNT_PAIRS])
             done += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
                                "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "one step of each of the first %d of the 1024 runs, "
-                                         "oracle (plain C, one thread)" % done}
+                               "sample": "%d run-steps (the 1024 runs in turn, each from its "
+                                         "initial state), oracle (plain C, one thread)" % done}
     b.close()
     ctx.close()
     return out
