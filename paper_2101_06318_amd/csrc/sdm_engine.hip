@@ -957,17 +957,28 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     if (tid == 0)
         s_misc[2] = 0;
 
-    // 1. this group's run in every tile; bucket and cell tables
-    for (int t = tid; t < nt; t += THREADS) {
-        const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t];
-        const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t];
+    const int c_lo = a.bucket_cell[b0];
+    const int n_gc = a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
+    // the tiles that can hold the group's records: all of them, except in a
+    // batch, whose runs occupy contiguous slot ranges (tiles t_first ..
+    // t_first + ntl - 1)
+    int t_first = 0, ntl = nt;
+    if (fused && a.seg_off) {
+        const uint32_t s_lo = a.seg_off[c_lo], s_hi = a.seg_off[c_lo + n_gc];
+        const uint32_t tile = (uint32_t)a.tile;
+        t_first = s_hi > s_lo ? (int)(s_lo / tile) : 0;
+        ntl = s_hi > s_lo ? min(nt - 1, (int)((s_hi - 1) / tile)) - t_first + 1 : 0;
+    }
+
+    // 1. this group's run in each of those tiles; bucket and cell tables
+    for (int t = tid; t < ntl; t += THREADS) {
+        const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
+        const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
         run_lo[t] = (uint16_t)lo;
         run_pre[t] = hi - lo;
     }
     for (int i = tid; i <= nb; i += THREADS)
         t_off[i] = a.bucket_start[b0 + i] - rank0;
-    const int c_lo = a.bucket_cell[b0];
-    const int n_gc = a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
     for (int i = tid; i <= n_gc; i += THREADS) {
         const int c = c_lo + i;
         if (i < n_gc) {
@@ -997,7 +1008,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             t_pc[i] = pair_ctx(a, c, cs, n_c);
     }
     __syncthreads();
-    lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, nt, red);
+    lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, ntl, red);
     if (tid < 64) {  // nb <= MAXB = 64: one wave scans the sub-bucket counts
         const uint32_t ns = tid < nb ? t_subbase[tid] : 0u;
         const uint32_t inc = wave_inclusive_scan(ns);
@@ -1022,7 +1033,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
         uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);  // tile of each gathered slot
         const uint32_t nsub = t_subbase[nb];
-        for (int t = tid; t < nt; t += THREADS)
+        for (int t = tid; t < ntl; t += THREADS)
             for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
                 tmap[li] = (uint16_t)t;
         __syncthreads();
@@ -1042,7 +1053,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             vv[e] = 0.0;
             if (li < tot) {
                 const int t = tmap[li];
-                const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
+                const int64_t pos =
+                    (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
                 if (fused) {
                     const RecA ra = a.rec_a[pos];
                     sid[e] = (uint32_t)ra.sk;
@@ -1323,8 +1335,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     while (P < tot)
         P <<= 1;
     for (uint32_t li = tid; li < tot; li += THREADS) {
-        const int t = upper_index(run_pre, nt, li);
-        const int64_t pos = (int64_t)t * a.tile + run_lo[t] + (li - run_pre[t]);
+        const int t = upper_index(run_pre, ntl, li);
+        const int64_t pos = (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
         const uint32_t s = fused ? (uint32_t)a.rec_a[pos].sk : a.rec_k[pos].s;
         const uint64_t k =
             fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
