@@ -8,7 +8,7 @@
 //  k_tile    one workgroup per tile of T SD slots (coalesced reads of xi and
 //            v): Step 0 liveness (xi > 0), Philox shuffle key, bucket =
 //            (cell, top key bits); an LDS counting sort by bucket, then the
-//            tile's records (id with the key's top 32 bits, xi, v) are
+//            tile's records (id, 24 key bits and the bucket, xi, v) are
 //            written contiguously through LDS staging, with the tile's
 //            per-bucket offsets.  No global atomics except one per tile
 //            (live total).
@@ -379,7 +379,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     }
     __syncthreads();
 
-    // list modes keep whole keys; the fused mode keeps the top 32 bits and,
+    // list modes keep whole keys; the fused mode keeps 24 key bits and the
+    // bucket's low 8 bits (the record's high word) and,
     // with up to 8 slots per thread (registers allow it), loads the volumes
     // together with xi
     constexpr bool EARLY_V = !LIST && EPT <= 8;
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             if (LIST)
                 key[j] = kk[e];
             else
-                k32[j] = (uint32_t)(kk[e] >> 21);
+                k32[j] = 0;
             xv[j] = x[e];
             if (LIST)
                 sid[j] = s[e];
@@ -511,6 +512,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                 const uint32_t b = bb + (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
                 const uint32_t r = atomicAdd(&hist[b], 1u);
                 bk[j] = b | (r << 16);
+                if (!LIST)  // the 24 key bits below the bucket's, and the bucket's low 8 bits
+                    k32[j] = ((uint32_t)(kk[e] >> (29 - h)) & 0xFFFFFFu) | (b << 24);
             }
         }
     }
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         pos[j] = b == NO_BUCKET ? 0xFFFFFFFFu : hist[b] + (bk[j] >> 16);
     }
     // staged, coalesced write-out of the tile's records in bucket order.
-    // Fused mode: id and the key's top 32 bits in one word, then (xi, v);
+    // Fused mode: one 24-B record (id, 24 key bits and the bucket, xi, v);
     // list modes: (key, id).  Passes of a.chunk 16-B records.
     const int64_t rbase = (int64_t)blockIdx.x * T;
     const uint32_t CH = a.chunk;
@@ -920,7 +923,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     constexpr int NSUB = CAP;  // sub-buckets per group
     __shared__ uint32_t t_off[MAXB + 1];
     __shared__ uint32_t t_subbase[MAXB + 1];
-    __shared__ uint32_t t_shift[MAXB];
+    __shared__ uint32_t t_shift[MAXB];     // sub-bucket shift: whole keys (list modes) or the 24 stored key bits
+    __shared__ uint8_t t_cl[MAXB];         // the bucket's cell among the group's cells
     __shared__ uint32_t t_mask[MAXB];
     __shared__ uint32_t t_cs[MAXB];
     __shared__ uint32_t t_n[MAXB];
@@ -994,7 +998,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         const int c = a.bucket_cell[b];
         const int h = a.cell_h[c];
         const int u = a.sub_bits[b];
-        t_shift[i] = (uint32_t)(53 - h - u);
+        t_shift[i] = (uint32_t)(fused ? 24 - u : 53 - h - u);
+        t_cl[i] = (uint8_t)(c - c_lo);
         t_mask[i] = (1u << u) - 1u;
         t_subbase[i] = 1u << u;
         const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
@@ -1037,9 +1042,10 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
                 tmap[li] = (uint16_t)t;
         __syncthreads();
-        // fused mode: key[] holds the top 32 bits of the 53-bit key (bits
-        // 52..21); they fix the bucket and sub-bucket (h + u <= 32), and the
-        // rank falls back to the whole key only between equal top bits
+        // fused mode: the record carries the 24 key bits below its bucket's
+        // (bits 28 - h .. 52 - h) and the bucket's low 8 bits; they fix the
+        // bucket and sub-bucket (u <= 24), and the rank falls back to the
+        // whole key only between equal stored bits
         uint64_t key[EPT], xv[EPT];
         double vv[EPT];
         uint32_t sid[EPT], sbk[EPT], fp[EPT];
@@ -1058,7 +1064,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 if (fused) {
                     const RecA ra = a.rec_a[pos];
                     sid[e] = (uint32_t)ra.sk;
-                    key[e] = (ra.sk >> 32) << 21;
+                    key[e] = ra.sk >> 32;  // 24 key bits | bucket low 8 bits << 24
                     xv[e] = ra.xi;
                     vv[e] = ra.v;
                 } else {
@@ -1077,16 +1083,24 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             gcl[e] = 0;
             fp[e] = 0;
             if (li < tot) {
-                // the record's cell among the group's cells
-                int cl = 0;
-                if (a.seg_off)
-                    cl = upper_index(g_seg, n_gc, sid[e]);
-                else if (a.cell_id && n_gc > 1)
-                    cl = a.cell_id[sid[e]] - c_lo;
-                gcl[e] = (uint8_t)cl;
-                const uint32_t h = g_ch[cl];
-                const uint32_t bl = g_cbb[cl] - (uint32_t)b0 +
-                                    (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
+                uint32_t bl;
+                if (fused) {
+                    // the bucket from its low 8 bits (a group spans < 256
+                    // buckets); key[] keeps the 24 key bits
+                    bl = ((uint32_t)(key[e] >> 24) - (uint32_t)b0) & 255u;
+                    key[e] &= 0xFFFFFFu;
+                    gcl[e] = t_cl[bl];
+                } else {
+                    // the record's cell among the group's cells
+                    int cl = 0;
+                    if (a.seg_off)
+                        cl = upper_index(g_seg, n_gc, sid[e]);
+                    else if (a.cell_id && n_gc > 1)
+                        cl = a.cell_id[sid[e]] - c_lo;
+                    gcl[e] = (uint8_t)cl;
+                    const uint32_t h = g_ch[cl];
+                    bl = g_cbb[cl] - (uint32_t)b0 + (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
+                }
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
                 blk[e] = (uint8_t)bl;
                 sbk[e] = t_subbase[bl] + sub;
@@ -1097,8 +1111,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         lds_exclusive_scan<THREADS, (NSUB + THREADS - 1) / THREADS>(sub_hist, (int)nsub, red);
         // rank by (key, s) inside the sub-bucket: the first RW entries of
         // every sub-bucket with independent (predicated) loads, the rare
-        // longer ones in a loop.  Fused mode sorts (top 32 key bits, id)
-        // words and settles equal top bits by the whole keys.
+        // longer ones in a loop.  Fused mode sorts (24 stored key bits, id)
+        // words and settles equal stored bits by the whole keys.
         constexpr uint32_t RW = 4;
         uint32_t rlo[EPT], rhi[EPT];
         uint32_t tie = 0;  // bit e: record e met an equal key (other id)
@@ -1107,7 +1121,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
                 if (sbk[e] != 0xFFFFFFFFu)
-                    KS[sub_hist[sbk[e]] + fp[e]] = ((key[e] >> 21) << 32) | sid[e];
+                    KS[sub_hist[sbk[e]] + fp[e]] = (key[e] << 32) | sid[e];
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -1117,7 +1131,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             }
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const uint32_t hm = (uint32_t)(key[e] >> 21);
+                const uint32_t hm = (uint32_t)key[e];
                 uint32_t r = 0;
 #pragma unroll
                 for (uint32_t j = 0; j < RW; ++j) {
@@ -1142,12 +1156,12 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 for (int e = 0; e < EPT; ++e) {
                     if (!((tie >> e) & 1u))
                         continue;
-                    // equal top bits: the whole keys (same cell, so the same
+                    // equal stored bits: the whole keys (same cell, so the same
                     // run) decide, then the ids
                     const int cl = gcl[e];
                     const uint32_t so = a.seg_off ? g_seg[cl] : 0u;
                     const uint32_t run = g_run[cl];
-                    const uint32_t hm = (uint32_t)(key[e] >> 21);
+                    const uint32_t hm = (uint32_t)key[e];
                     const uint64_t km =
                         philox_word(a.seed, run, step, SDM_STREAM_SHUFFLE, sid[e] - so) >> 11;
                     for (uint32_t q = rlo[e]; q < rhi[e]; ++q) {
@@ -1555,10 +1569,10 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             int u = 0;
             while (e / std::ldexp(1.0, u + 1) >= 1.0 && u < nsub_bits)
                 ++u;
-            // the group kernel finds bucket and sub-bucket in the key's top
-            // 32 bits
-            if (h + u > 32)
-                throw HipError{hipErrorInvalidValue, "key bits of a bucket exceed 32"};
+            // the group kernel finds the sub-bucket in the 24 key bits below
+            // the bucket's (fused records)
+            if (u > 24 || h > 29)
+                throw HipError{hipErrorInvalidValue, "key bits of a bucket exceed the record"};
             for (int i = 0; i < (1 << h); ++i) {
                 bucket_cell.push_back(c);
                 sub_bits.push_back((uint8_t)u);

@@ -60,9 +60,10 @@ struct HipError {
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
 // One SD's record between the tile and group kernels.  List modes: (shuffle
-// key, id).  Fused step: id with the key's top 32 bits in the high word,
-// multiplicity and volume (24 B); the group kernel draws the whole key again
-// only for records whose top bits tie.
+// key, id).  Fused step: id in the low word; in the high word the 24 key
+// bits below the bucket's and the bucket's low 8 bits; multiplicity and
+// volume (24 B).  The group kernel draws the whole key again only for
+// records whose stored bits tie.
 struct __attribute__((aligned(16))) RecK {
     uint64_t key;
     uint32_t s;
