@@ -1050,28 +1050,35 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         double vv[EPT];
         uint32_t sid[EPT], sbk[EPT], fp[EPT];
         uint8_t blk[EPT], gcl[EPT];
+        // every thread loads all its slots unconditionally (slots past tot
+        // repeat the last record and are dropped below), so that the loads
+        // of all EPT records are in flight together
+        const uint32_t last = tot > 0 ? tot - 1 : 0;
+        if (tot > 0 && fused) {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t li = (uint32_t)(e * THREADS + tid);
-            key[e] = 0;
-            sid[e] = 0;
-            xv[e] = 0;
-            vv[e] = 0.0;
-            if (li < tot) {
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
                 const int t = tmap[li];
                 const int64_t pos =
                     (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
-                if (fused) {
-                    const RecA ra = a.rec_a[pos];
-                    sid[e] = (uint32_t)ra.sk;
-                    key[e] = ra.sk >> 32;  // 24 key bits | bucket low 8 bits << 24
-                    xv[e] = ra.xi;
-                    vv[e] = ra.v;
-                } else {
-                    const RecK rk = a.rec_k[pos];
-                    key[e] = rk.key;
-                    sid[e] = rk.s;
-                }
+                const RecA ra = a.rec_a[pos];
+                sid[e] = (uint32_t)ra.sk;
+                key[e] = ra.sk >> 32;  // 24 key bits | bucket low 8 bits << 24
+                xv[e] = ra.xi;
+                vv[e] = ra.v;
+            }
+        } else if (tot > 0) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
+                const int t = tmap[li];
+                const int64_t pos =
+                    (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
+                const RecK rk = a.rec_k[pos];
+                key[e] = rk.key;
+                sid[e] = rk.s;
+                xv[e] = 0;
+                vv[e] = 0.0;
             }
         }
         const uint32_t step = step_of(a.step, a.step_dev);
