@@ -392,6 +392,35 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     uint32_t sid[LIST ? EPT : 1];
     const int seg_n = segtab ? st_n : 0;
 
+    // fused mode, up to 8 slots per thread (small launches, latency bound):
+    // every slot pair's loads (xi, v, cell ids) are issued before any of
+    // them is used, from clamped addresses, so that they are all in flight
+    // together; the odd last slot of the launch is read on its own below.
+    // With 16 slots per thread (bandwidth bound) each pair is loaded where
+    // it is used, which overlaps the loads with the key arithmetic.
+    constexpr bool PRELOAD = !LIST && EPT <= 8;
+    constexpr bool EARLY_CID = PRELOAD;
+    uint32_t cid[EARLY_CID ? EPT : 1];
+    if (PRELOAD && n_items >= 2) {
+#pragma unroll
+        for (int k = 0; k < EPT / 2; ++k) {
+            const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
+            const int64_t ia = i0 + 1 < n_items ? i0 : 0;
+            const ulonglong2 xx = *reinterpret_cast<const ulonglong2 *>(a.xi + ia);
+            xv[2 * k] = xx.x;
+            xv[2 * k + 1] = xx.y;
+            if (EARLY_V) {
+                const double2 v2 = *reinterpret_cast<const double2 *>(a.v + ia);
+                vv[2 * k] = v2.x;
+                vv[2 * k + 1] = v2.y;
+            }
+            if (EARLY_CID && a.cell_id) {
+                cid[2 * k] = (uint32_t)a.cell_id[ia];
+                cid[2 * k + 1] = (uint32_t)a.cell_id[ia + 1];
+            }
+        }
+    }
+
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
         const int64_t p = pair0 + (int64_t)k * THREADS + tid;
@@ -404,7 +433,14 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             s[0] = (uint32_t)i0;
             s[1] = (uint32_t)(i0 + 1);
             double v[2] = {0.0, 0.0};
-            if (i0 + 1 < n_items) {
+            if (i0 + 1 < n_items && PRELOAD) {
+                x[0] = xv[2 * k];
+                x[1] = xv[2 * k + 1];
+                if (EARLY_V) {
+                    v[0] = vv[2 * k];
+                    v[1] = vv[2 * k + 1];
+                }
+            } else if (i0 + 1 < n_items) {
                 const ulonglong2 xx = *reinterpret_cast<const ulonglong2 *>(a.xi + i0);
                 x[0] = xx.x;
                 x[1] = xx.y;
@@ -453,6 +489,10 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             for (int e = 0; e < 2; ++e)
                 if (s[e] - a.seg_off[cell[e]] >= a.seg_len[cell[e]])
                     live[e] = false;
+        } else if (EARLY_CID && i0 + 1 < n_items) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                cell[e] = (a.cell_id && live[e]) ? (int32_t)cid[2 * k + e] : 0;
         } else {
 #pragma unroll
             for (int e = 0; e < 2; ++e)
