@@ -296,14 +296,22 @@ __global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
     const int c0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
     const int64_t Bp = a.B + 1;
     const int c = c0 + lane;
+    // all 64 / W rows of a wave in flight together: clamped addresses,
+    // out-of-range entries dropped after the load
     uint32_t sum = 0;
-    for (int i = w; i < 64; i += W) {
-        const int t = t0 + i;
-        uint16_t v = 0;
-        if (t < a.n_tiles && c <= a.B)
-            v = a.tile_off[t * Bp + c];
-        blk[i][lane] = v;
-        sum += v;
+    const int cc0 = min(c, a.B);
+    uint16_t v[64 / W];
+#pragma unroll
+    for (int j = 0; j < 64 / W; ++j) {
+        const int t = min(t0 + w + j * W, a.n_tiles - 1);
+        v[j] = a.tile_off[t * Bp + cc0];
+    }
+#pragma unroll
+    for (int j = 0; j < 64 / W; ++j) {
+        const int i = w + j * W;
+        const uint16_t x = (t0 + i < a.n_tiles && c <= a.B) ? v[j] : (uint16_t)0;
+        blk[i][lane] = x;
+        sum += x;
     }
     part[w][lane] = sum;
     __syncthreads();
