@@ -246,8 +246,19 @@ __global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
 {
     __shared__ u32x4 sw[FWD_FRAGS * 64];
     __shared__ float sb[3 * NH + 4];
-    for (int i = threadIdx.x; i < FWD_FRAGS * 64; i += 256)
-        sw[i] = packed[i];
+    // staged 8 loads per thread at a time (clamped, so that all 8 are in
+    // flight together), then written to LDS
+    constexpr int NF = FWD_FRAGS * 64;
+    for (int i0 = threadIdx.x; i0 < NF; i0 += 256 * 8) {
+        u32x4 r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            r[j] = packed[min(i0 + 256 * j, NF - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (i0 + 256 * j < NF)
+                sw[i0 + 256 * j] = r[j];
+    }
     for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 256)
         sb[i] = P[i < NH ? OFF_B1 + i
                   : i < 2 * NH ? OFF_B2 + (i - NH)
