@@ -971,7 +971,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     constexpr int NSUB = CAP;  // sub-buckets per group
     __shared__ uint32_t t_off[MAXB + 1];
     __shared__ uint32_t t_subbase[MAXB + 1];
-    __shared__ uint32_t t_shift[MAXB];     // sub-bucket shift: whole keys (list modes) or the 24 stored key bits
+    __shared__ uint32_t t_shift[MAXB];     // sub-bucket shift (whole key, or the 24 stored bits)
     __shared__ uint8_t t_cl[MAXB];         // the bucket's cell among the group's cells
     __shared__ uint32_t t_mask[MAXB];
     __shared__ uint32_t t_cs[MAXB];
@@ -1269,14 +1269,18 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         uint64_t *RX = reinterpret_cast<uint64_t *>(pool);
         double *RV = reinterpret_cast<double *>(pool + 8 * CAP);
         uint32_t *RS = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
+        // position -> slot: the low two bits XORed with bits 4-5, so that
+        // lanes reading positions 4 apart (two pairs per thread) hit
+        // different LDS banks; a permutation within every 4 positions
+        auto sw = [](uint32_t f) { return f ^ ((f >> 4) & 3u); };
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             if (sbk[e] == 0xFFFFFFFFu)
                 continue;
             const uint32_t f = fp[e];
-            RX[f] = xv[e];
-            RV[f] = vv[e];
-            RS[f] = sid[e];
+            RX[sw(f)] = xv[e];
+            RV[sw(f)] = vv[e];
+            RS[sw(f)] = sid[e];
         }
         if (tid < 64) {
             // pairs of every bucket: openers at even in-cell indices whose
@@ -1303,7 +1307,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
         __syncthreads();
         for (uint32_t f = tid; f < tot; f += THREADS)
-            a.idx_out[rank0 + f] = RS[f];
+            a.idx_out[rank0 + f] = RS[sw(f)];
         if (tid == 0 && tot > 0) {
             // a closer at position 0 and an opener at position tot - 1 pair
             // with the neighbouring groups (k_finish)
@@ -1317,9 +1321,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 if (!seam)
                     continue;
                 SeamRec rec;
-                rec.xi = RX[f];
-                rec.v = RV[f];
-                rec.s = RS[f];
+                rec.xi = RX[sw(f)];
+                rec.v = RV[sw(f)];
+                rec.s = RS[sw(f)];
                 rec.rank = rank0 + f;
                 rec.cell = a.bucket_cell[b0 + bl];
                 rec.cs = cs;
@@ -1363,7 +1367,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 fv[u] = f;
                 runv[u] = pc.run;
                 qv[u] = (rank0 + f - pc.slot_base) >> 1;
-                pv[u] = pair_prob(pc, RX[f], RV[f], RX[f + 1], RV[f + 1]);
+                pv[u] =
+                    pair_prob(pc, RX[sw(f)], RV[sw(f)], RX[sw(f + 1)], RV[sw(f + 1)]);
             }
             double phi[2] = {0.0, 0.0};
             if (valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1u && runv[0] == runv[1]) {
@@ -1383,8 +1388,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 if (!valid[u])
                     continue;
                 const uint32_t f = fv[u];
-                finish_pair_v(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[f], RX[f], RV[f],
-                              RS[f + 1], RX[f + 1], RV[f + 1], st);
+                finish_pair_v(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[sw(f)], RX[sw(f)],
+                              RV[sw(f)], RS[sw(f + 1)], RX[sw(f + 1)], RV[sw(f + 1)], st);
             }
         }
         if (a.counters)
