@@ -43,14 +43,14 @@ constexpr int TILE_THREADS = 1024;
 constexpr int TILE_EPT_MAX = 16;  // SD slots per tile thread (4, 8 or 16 per plan)
 constexpr int TILE_FILL = 256;    // tiles that fill the GPU (one per CU)
 constexpr int GROUP_THREADS = 512;
-constexpr int GROUP_EPT_S = 6;       // records per group thread: the usual plans
+constexpr int GROUP_EPT_S = 7;       // records per group thread: the usual plans
 constexpr int GROUP_EPT_L = 8;       // plans whose buckets hold more than GROUP_TARGET SDs
 constexpr int MAXB = 32;             // buckets per group
 constexpr int MAX_TILES = 2048;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
 constexpr double BUCKET_TARGET = 1024.0;
-constexpr double GROUP_TARGET = 2400.0;  // expected SDs per group of GROUP_EPT_S plans
+constexpr double GROUP_TARGET = 3100.0;  // expected SDs per group of GROUP_EPT_S plans
 constexpr uint32_t NO_BUCKET = 0xFFFFu;
 
 __device__ __forceinline__ uint32_t load32_agent(const uint32_t *p)
@@ -988,10 +988,11 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t sub_hist[NSUB + 1];
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
-    // gather: tile map and the group's run in every tile; sort: keys and
-    // ids by sub-bucket position (12 B per record); afterwards the records
-    // in sorted order (fused mode: xi, v, id, 20 B per record)
-    __shared__ __align__(16) unsigned char pool[CAP * 20];
+    // gather: tile map and the group's run in every tile; sort: (key bits,
+    // id) words by sub-bucket position; afterwards the records in sorted
+    // order (fused mode: xi and v, 16 B per record; their ids go to the
+    // sub-bucket table, dead by then)
+    __shared__ __align__(16) unsigned char pool[CAP * 16];
     static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 2 * MAX_TILES <= 12 * CAP,
                   "run tables must fit the sort pool");
     uint32_t *run_pre = reinterpret_cast<uint32_t *>(pool + 2 * CAP);
@@ -1268,7 +1269,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         // 3. the records in sorted order (SoA in the pool), idx, seams
         uint64_t *RX = reinterpret_cast<uint64_t *>(pool);
         double *RV = reinterpret_cast<double *>(pool + 8 * CAP);
-        uint32_t *RS = reinterpret_cast<uint32_t *>(pool + 16 * CAP);
+        uint32_t *RS = sub_hist;  // the sub-bucket table is dead after the ranks
         // position -> slot: the low two bits XORed with bits 4-5, so that
         // lanes reading positions 4 apart (two pairs per thread) hit
         // different LDS banks; a permutation within every 4 positions
@@ -1729,7 +1730,10 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
         return it->second;
     std::vector<double> exp(n_cell, expected_per_cell);
     const double bt = ctx->dbg_bucket_target > 0 ? (double)ctx->dbg_bucket_target : BUCKET_TARGET;
-    Plan *p = build_plan(ctx, mode, n_items, exp, bt, GROUP_TARGET);
+    // small launches: smaller groups (at least two per CU where the buckets
+    // allow), since parallelism, not per-group overhead, limits them
+    const double gt = std::min(GROUP_TARGET, std::max(1024.0, (double)n_items / 512.0));
+    Plan *p = build_plan(ctx, mode, n_items, exp, bt, gt);
     ctx->plans[key] = p;
     return p;
 }
@@ -1737,8 +1741,8 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
 // Schedules the batch autotuner chooses from: (expected SDs per key bucket,
 // expected SDs per group).  Results never depend on the choice.
 static const double kSchedules[][2] = {
-    {1024.0, 2400.0}, {512.0, 2400.0}, {2048.0, 2400.0},
-    {1024.0, 1800.0}, {512.0, 1800.0}, {512.0, 1200.0},
+    {1024.0, 3100.0}, {512.0, 3100.0}, {2048.0, 3100.0},
+    {1024.0, 2400.0}, {512.0, 2400.0}, {512.0, 1600.0},
 };
 int n_schedules() { return (int)(sizeof(kSchedules) / sizeof(kSchedules[0])); }
 
