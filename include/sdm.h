@@ -244,7 +244,8 @@ typedef struct {
     double            expected_per_cell; /* planning hint (0 => n_sd/n_cell)*/
     hipEvent_t        events[4];     /* optional (NULL entries skipped):    */
                                      /* recorded on the stream before the   */
-                                     /* partition kernels (tile, scans),    */
+                                     /* partition kernels (tile, column     */
+                                     /* sums),                              */
                                      /* the group kernel, the finish kernel */
                                      /* and after it, for timing            */
 } sdm_step_params;
