@@ -993,10 +993,12 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     // order (fused mode: xi and v, 16 B per record; their ids go to the
     // sub-bucket table, dead by then)
     __shared__ __align__(16) unsigned char pool[CAP * 16];
-    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 2 * MAX_TILES <= 12 * CAP,
+    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= 16 * CAP,
                   "run tables must fit the sort pool");
+    // run_pre: the group's records before each tile's run; run_base: the
+    // record slot of a group position li in tile t is run_base[t] + li
     uint32_t *run_pre = reinterpret_cast<uint32_t *>(pool + 2 * CAP);
-    uint16_t *run_lo = reinterpret_cast<uint16_t *>(pool + 2 * CAP + 4 * (MAX_TILES + 1));
+    uint32_t *run_base = reinterpret_cast<uint32_t *>(pool + 2 * CAP + 4 * (MAX_TILES + 1));
 
     const int tid = threadIdx.x;
     const int g = blockIdx.x;
@@ -1027,7 +1029,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (int t = tid; t < ntl; t += THREADS) {
         const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
         const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
-        run_lo[t] = (uint16_t)lo;
+        run_base[t] = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
         run_pre[t] = hi - lo;
     }
     for (int i = tid; i <= nb; i += THREADS)
@@ -1063,7 +1065,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     }
     __syncthreads();
     lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, ntl, red);
-    if (tid < 64) {  // nb <= MAXB = 64: one wave scans the sub-bucket counts
+    for (int t = tid; t < ntl; t += THREADS)
+        run_base[t] -= run_pre[t];  // modulo 2^32; run_base[t] + li is the slot
+    if (tid < 64) {  // nb <= MAXB <= 64: one wave scans the sub-bucket counts
         const uint32_t ns = tid < nb ? t_subbase[tid] : 0u;
         const uint32_t inc = wave_inclusive_scan(ns);
         if (tid < nb)
@@ -1108,8 +1112,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             for (int e = 0; e < EPT; ++e) {
                 const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
                 const int t = tmap[li];
-                const int64_t pos =
-                    (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
+                const uint32_t pos = run_base[t] + li;
                 const RecA ra = a.rec_a[pos];
                 sid[e] = (uint32_t)ra.sk;
                 key[e] = ra.sk >> 32;  // 24 key bits | bucket low 8 bits << 24
@@ -1121,8 +1124,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             for (int e = 0; e < EPT; ++e) {
                 const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
                 const int t = tmap[li];
-                const int64_t pos =
-                    (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
+                const uint32_t pos = run_base[t] + li;
                 const RecK rk = a.rec_k[pos];
                 key[e] = rk.key;
                 sid[e] = rk.s;
@@ -1411,7 +1413,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         P <<= 1;
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, ntl, li);
-        const int64_t pos = (int64_t)(t_first + t) * a.tile + run_lo[t] + (li - run_pre[t]);
+        const uint32_t pos = run_base[t] + li;
         const uint32_t s = fused ? (uint32_t)a.rec_a[pos].sk : a.rec_k[pos].s;
         const uint64_t k =
             fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
