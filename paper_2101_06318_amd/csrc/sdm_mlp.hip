@@ -15,6 +15,10 @@
 // and the weights are stored ("packed") with the same permutation, so the
 // activations never leave the registers between layers.
 //
+// Inference batches of up to a few tiles per SIMD use a variant in which
+// four waves share a tile's hidden layers (k_mlp_forward_split), which
+// spreads the GELU work over more waves.
+//
 // Weight gradients dW = dZ^T A sum over samples, a different operand
 // layout; there the workgroup stages dZ^T and A^T of its 64 samples in LDS
 // and each wave takes a share of the output tiles.  Per-workgroup partial
@@ -47,6 +51,7 @@ constexpr int BWD_CHUNK = 64;      // samples per backward workgroup pass
 constexpr int BWD_ROW = 72;        // LDS row stride (bf16): 64 samples + 8 pad
 constexpr int PART_ROWS_MAX = 128; // backward workgroups (partial-sum rows)
 constexpr int FWD_GRID_MAX = 512;  // forward workgroups (two per CU)
+constexpr int64_t SPLIT_MAX_TILES = 16384;  // largest inference batch (16-sample tiles) for the split forward
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -174,6 +179,9 @@ __device__ inline void hidden_layer(const u32x4 *__restrict__ frags, int layer,
                 acc[j] = mfma(a, in[j][q], acc[j]);
         }
         hidden_epilogue<S, TRAIN>(acc, t, layer, sb, out, cache, tile0, n_tiles, lane);
+        // one output tile's fragments at a time: left free, the scheduler
+        // hoists the LDS reads of all eight tiles and the kernel spills
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -205,6 +213,7 @@ __device__ inline void forward_tiles(float *__restrict__ y, float *__restrict__ 
         for (int j = 0; j < S; ++j)
             acc[j] = mfma(a, bx[j], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
         hidden_epilogue<S, TRAIN>(acc, t, 0, sb, ha, cache, tile0, n_tiles, lane);
+        __builtin_amdgcn_sched_barrier(0);
     }
     hidden_layer<S, TRAIN>(sw + FR_F2 * 64, 1, sb, ha, hb, cache, tile0, n_tiles, lane);
     hidden_layer<S, TRAIN>(sw + FR_F3 * 64, 2, sb, hb, ha, cache, tile0, n_tiles, lane);
@@ -246,18 +255,19 @@ __global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
 {
     __shared__ u32x4 sw[FWD_FRAGS * 64];
     __shared__ float sb[3 * NH + 4];
-    // staged 8 loads per thread at a time (clamped, so that all 8 are in
-    // flight together), then written to LDS
+    // staged with all of a thread's loads in flight together, then written
+    // to LDS
     constexpr int NF = FWD_FRAGS * 64;
-    for (int i0 = threadIdx.x; i0 < NF; i0 += 256 * 8) {
-        u32x4 r[8];
+    constexpr int PER = NF / 256;
+    static_assert(NF % 256 == 0, "fragments per thread");
+    {
+        u32x4 r[PER];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            r[j] = packed[min(i0 + 256 * j, NF - 1)];
+        for (int j = 0; j < PER; ++j)
+            r[j] = packed[threadIdx.x + 256 * j];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (i0 + 256 * j < NF)
-                sw[i0 + 256 * j] = r[j];
+        for (int j = 0; j < PER; ++j)
+            sw[threadIdx.x + 256 * j] = r[j];
     }
     for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 256)
         sb[i] = P[i < NH ? OFF_B1 + i
@@ -273,6 +283,109 @@ __global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
         forward_tiles<S, TRAIN>(y, cache, x, B, sw, sb, tile0, n_tiles, lane, r, g);
 }
 
+
+// Forward pass for batches that leave every SIMD about one 16-sample tile.
+// A workgroup of 16 waves takes 4 tiles, and the 4 waves of a tile share
+// each hidden layer: wave f computes output tiles 2f and 2f + 1, which make
+// up K-step f of the next layer's operand, and the waves swap their K-steps
+// through LDS.  The GELU work of a tile then runs on four waves that
+// interleave on the SIMDs instead of one.
+constexpr int SPLIT_TILES = 4;
+
+__device__ inline u32x4 split_epilogue(const f32x4 &a0, const f32x4 &a1, int t0, int layer,
+                                       const float *__restrict__ sb, int g)
+{
+    float h0[4], h1[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        h0[e] = gelu(a0[e] + sb[layer * NH + 16 * t0 + 4 * g + e]);
+        h1[e] = gelu(a1[e] + sb[layer * NH + 16 * (t0 + 1) + 4 * g + e]);
+    }
+    return u32x4{pack2(h0[0], h0[1]), pack2(h0[2], h0[3]), pack2(h1[0], h1[1]),
+                 pack2(h1[2], h1[3])};
+}
+
+__global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ y,
+                                                           const float *__restrict__ x,
+                                                           int64_t B,
+                                                           const u32x4 *__restrict__ packed,
+                                                           const float *__restrict__ P)
+{
+    __shared__ u32x4 sw[FWD_FRAGS * 64];
+    __shared__ float sb[3 * NH + 4];
+    // K-steps of the three hidden layers' outputs, one buffer per layer, so
+    // that a layer's writes never meet the reads of the layer before
+    __shared__ u32x4 xk[3][SPLIT_TILES][4][64];
+    constexpr int NF = FWD_FRAGS * 64;
+    constexpr int PER = (NF + 1023) / 1024;
+    {
+        u32x4 r[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            r[j] = packed[min((int)threadIdx.x + 1024 * j, NF - 1)];
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if ((int)threadIdx.x + 1024 * j < NF)
+                sw[threadIdx.x + 1024 * j] = r[j];
+    }
+    for (int i = threadIdx.x; i < 3 * NH + NOUT; i += 1024)
+        sb[i] = P[i < NH ? OFF_B1 + i
+                  : i < 2 * NH ? OFF_B2 + (i - NH)
+                  : i < 3 * NH ? OFF_B3 + (i - 2 * NH)
+                               : OFF_B4 + (i - 3 * NH)];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = w >> 2, f = w & 3, r = lane & 15, g = lane >> 4;
+    const int64_t n_sets = ((B + 15) / 16 + SPLIT_TILES - 1) / SPLIT_TILES;
+    const f32x4 zero{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t set = blockIdx.x; set < n_sets; set += gridDim.x) {
+        const int64_t s = (set * SPLIT_TILES + i) * 16 + r;
+        // layer 1: the K x N operand is x itself (features 8g..8g+7 of sample r)
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            v[e] = (k < NIN && s < B) ? x[s * NIN + k] : 0.0f;
+        }
+        const u32x4 bx{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+        {
+            const f32x4 a0 = mfma(sw[(FR_F1 + 2 * f) * 64 + lane], bx, zero);
+            const f32x4 a1 = mfma(sw[(FR_F1 + 2 * f + 1) * 64 + lane], bx, zero);
+            xk[0][i][f][lane] = split_epilogue(a0, a1, 2 * f, 0, sb, g);
+        }
+        __syncthreads();
+        // layers 2 and 3
+#pragma unroll
+        for (int layer = 1; layer <= 2; ++layer) {
+            const u32x4 *fr = sw + (layer == 1 ? FR_F2 : FR_F3) * 64;
+            u32x4 in[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                in[q] = xk[layer - 1][i][q][lane];
+            f32x4 a0 = zero, a1 = zero;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a0 = mfma(fr[(8 * f + q) * 64 + lane], in[q], a0);
+                a1 = mfma(fr[(8 * f + 4 + q) * 64 + lane], in[q], a1);
+            }
+            xk[layer][i][f][lane] = split_epilogue(a0, a1, 2 * f, layer, sb, g);
+            __syncthreads();
+        }
+        // layer 4 (rows 0..2 of the 16-row output tile), by one wave per tile
+        if (f == 0) {
+            f32x4 acc = zero;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = mfma(sw[(FR_F4 + q) * 64 + lane], xk[2][i][q][lane], acc);
+            if (g == 0 && s < B) {
+#pragma unroll
+                for (int e = 0; e < NOUT; ++e)
+                    y[s * NOUT + e] = acc[e] + sb[3 * NH + e];
+            }
+        }
+    }
+}
 
 // ---------------------------------------------------------------- backward
 __device__ inline float sum16(float v)
@@ -652,19 +765,24 @@ int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_
     REQUIRE(B <= ((int64_t)1 << 34), "B too large");
     SDM_TRY
     const int64_t tiles = (B + 15) / 16;
-    // two tiles per wave pay off only once every workgroup has several
-    const int S = (!cache && tiles > 4 * 4 * FWD_GRID_MAX) ? 2 : 1;
-    const int64_t want = (tiles + 4 * S - 1) / (4 * S);
-    const int grid = (int)(want < FWD_GRID_MAX ? want : FWD_GRID_MAX);
-    if (cache)
-        hipLaunchKernelGGL((k_mlp_forward<1, true>), dim3(grid), dim3(256), 0, stream, y, cache,
-                           x, B, (const u32x4 *)w->packed, w->params);
-    else if (S == 1)
-        hipLaunchKernelGGL((k_mlp_forward<1, false>), dim3(grid), dim3(256), 0, stream, y,
-                           cache, x, B, (const u32x4 *)w->packed, w->params);
-    else
-        hipLaunchKernelGGL((k_mlp_forward<2, false>), dim3(grid), dim3(256), 0, stream, y,
-                           cache, x, B, (const u32x4 *)w->packed, w->params);
+    if (!cache && tiles <= SPLIT_MAX_TILES) {
+        // inference up to a few tiles per SIMD: four waves per tile
+        const int64_t sets = (tiles + SPLIT_TILES - 1) / SPLIT_TILES;
+        hipLaunchKernelGGL(k_mlp_forward_split, dim3((int)(sets < 256 ? sets : 256)), dim3(1024),
+                           0, stream, y, x, B, (const u32x4 *)w->packed, w->params);
+    } else {
+        // one wave per tile; inference takes two tiles at a time (larger
+        // batches only), training one, writing its pre-activations
+        const int S = cache ? 1 : 2;
+        const int64_t want = (tiles + 4 * S - 1) / (4 * S);
+        const int grid = (int)(want < FWD_GRID_MAX ? want : FWD_GRID_MAX);
+        if (cache)
+            hipLaunchKernelGGL((k_mlp_forward<1, true>), dim3(grid), dim3(256), 0, stream, y,
+                               cache, x, B, (const u32x4 *)w->packed, w->params);
+        else
+            hipLaunchKernelGGL((k_mlp_forward<2, false>), dim3(grid), dim3(256), 0, stream, y,
+                               cache, x, B, (const u32x4 *)w->packed, w->params);
+    }
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }
