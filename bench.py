@@ -22,6 +22,8 @@ Workloads (--workload, default box):
   surrogate  the moment surrogate's step for the 16384 cells of the grid
              (features, hull test, bf16 MFMA forward, moment update), beside
              one SDM step of the same grid (cell-steps/s of both).
+  train      the surrogate's training step: a minibatch of 4096 samples
+             through forward, MSE gradient, backward and Adam (samples/s).
 
 W warm-up steps run first.  Then K steps are captured in one HIP graph,
 replayed once untimed and five times timed, each bracketed by
@@ -592,13 +594,112 @@ def bench_surrogate(args, sdm, torch, np, workloads):
     return out
 
 
+MLP_TRAIN_BATCH = 4096
+MLP_BWD_FLOP_PER_SAMPLE = 133888.0  # dW of all four layers + dH of layers 4, 3, 2
+
+
+def bench_train(args, sdm, torch, np, workloads):
+    """Surrogate training: one step is one minibatch of 4096 samples through
+    the forward pass (keeping pre-activations), the MSE gradient, the
+    backward pass and Adam.  Synthetic standardised data: 2^20 samples (the
+    size of one training set of cell-steps) with standard-normal inputs and
+    targets, walked in order, a new batch every step.  Timed eagerly (Adam's
+    step count is a host argument, so the steps are not graph-captured)."""
+    n = 1 << 20
+    B = MLP_TRAIN_BATCH
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    X = torch.randn((n, 5), generator=g, device="cuda")
+    T = torch.randn((n, 3), generator=g, device="cuda")
+    ctx = sdm.Context(1 << 12, 1 << 12, 2)
+    net = sdm.Mlp(ctx, workloads.mlp_init(7))
+    y = torch.zeros((B, 3), dtype=torch.float32, device="cuda")
+    dy = torch.zeros_like(y)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    cache = sdm.Mlp.cache_for(B)
+    grad = torch.zeros(net.params.numel(), dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(grad)
+    v = torch.zeros_like(grad)
+    nb = n // B
+    lib = sdm.lib()
+
+    def train_step(t, stream, ev):
+        i = t % nb
+        xb, tb = X[i * B:(i + 1) * B], T[i * B:(i + 1) * B]
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.mlp_forward(y, xb, net, cache=cache, stream=stream)
+        ctx.mlp_mse(dy, loss, y, tb, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.mlp_backward(grad, dy, xb, cache, net, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+        ctx.mlp_adam(net, m, v, grad, t + 1, stream=stream)
+
+    for t in range(args.warmup):
+        train_step(t, None, None)
+    K = args.steps
+    ev = [[HipEvent(lib) for _ in range(3)] for _ in range(K)]
+    stream = torch.cuda.Stream()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        s0.record(stream)
+        for t in range(K):
+            train_step(args.warmup + t, stream, ev[t])
+        s1.record(stream)
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / K
+    fwd_ms = sum(e[0].elapsed_ms(e[1]) for e in ev) / K
+    bwd_ms = sum(e[1].elapsed_ms(e[2]) for e in ev) / K
+    for row in ev:
+        for e in row:
+            e.destroy()
+    achieved = MLP_BWD_FLOP_PER_SAMPLE * B / (bwd_ms / 1e3) / 1e12
+    out = base_line("surrogate training samples/s", B / (ms / 1e3), "samples/s", K,
+                    args.warmup, ms, "bf16",
+                    {"workload": "surrogate_train_batch_4096", "batch": B, "samples": n,
+                     "network": "5-128-128-128-3 GELU", "optimizer": "Adam",
+                     "step": "forward (with pre-activations) + MSE gradient + backward + Adam",
+                     "timing": TIMING_EAGER})
+    out["roofline"] = {"bound": "mfma", "kernel": "k_mlp_backward+k_mlp_reduce", "achieved": achieved,
+                       "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None}
+    out["kernel_ms"] = {"k_mlp_forward+k_mlp_mse": fwd_ms, "k_mlp_backward+k_mlp_reduce": bwd_ms}
+    out["flop_per_sample"] = MLP_FLOP_PER_SAMPLE + MLP_BWD_FLOP_PER_SAMPLE
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        from oracle import mlp
+        xh, th_t = X[:B].cpu().numpy(), T[:B].cpu().numpy()
+        th = workloads.mlp_init(7).astype(np.float64)
+        mo = np.zeros_like(th)
+        vo = np.zeros_like(th)
+        net_o = mlp.Net("bf16")
+        reps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            yo, c = net_o.forward(th, xh)
+            _, d = net_o.mse(yo, th_t)
+            go = net_o.backward(th, c, d)
+            th, mo, vo = mlp.adam(th, mo, vo, go, reps + 1)
+            reps += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": B * reps / dt, "unit": "samples/s", "cores": 1,
+                               "kind": "oracle", "seconds": round(dt, 3),
+                               "sample": "%d bf16-emulated training steps of 4096 samples "
+                                         "(numpy forward, MSE, backward, Adam)" % reps}
+    ctx.close()
+    return out
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="box",
-                    choices=["box", "grid", "ensemble", "golovin", "surrogate"])
+                    choices=["box", "grid", "ensemble", "golovin", "surrogate", "train"])
     ap.add_argument("--log2-n-sd", type=int, default=22)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time given to the oracle baseline (whole steps, at least one)")
@@ -632,7 +733,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     fn = {"box": bench_box, "grid": bench_grid, "ensemble": bench_ensemble,
-          "golovin": bench_golovin, "surrogate": bench_surrogate}[args.workload]
+          "golovin": bench_golovin, "surrogate": bench_surrogate,
+          "train": bench_train}[args.workload]
     out = fn(args, sdm, torch, np, workloads)
     print(json.dumps(out), flush=True)
 

@@ -619,7 +619,10 @@ __global__ void k_mlp_reduce(float *__restrict__ grad, const float *__restrict__
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAM)
         return;
+    // the rows in a fixed order; unrolled so that eight loads are in flight
+    // ahead of their (ordered) additions
     float acc = 0.0f;
+#pragma unroll 8
     for (int w = 0; w < rows; ++w)
         acc += part[(int64_t)w * NPARAM + i];
     grad[i] = acc;
@@ -632,6 +635,7 @@ __global__ __launch_bounds__(1024) void k_mlp_mse(float *__restrict__ dy, float 
     __shared__ float red[1024];
     const float scale = 2.0f / (float)n;
     float acc = 0.0f;
+#pragma unroll 4
     for (int64_t i = threadIdx.x; i < n; i += 1024) {
         const float d = yv[i] - tv[i];
         dy[i] = scale * d;
