@@ -463,6 +463,21 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
     __shared__ __attribute__((aligned(16))) uint16_t G[NH * BWD_ROW];
     __shared__ __attribute__((aligned(16))) uint16_t H[NH * BWD_ROW];
     __shared__ float bsum[4][NH];
+    // the transposed-weight fragments (B4, B3, B2: 72 KiB) in LDS, staged
+    // once with all of a thread's loads in flight
+    constexpr int NBF = (FR_N - FR_B4) * 64;
+    static_assert(NBF % 256 == 0, "fragments per thread");
+    __shared__ u32x4 sbw[NBF];
+    {
+        u32x4 rr[NBF / 256];
+#pragma unroll
+        for (int j = 0; j < NBF / 256; ++j)
+            rr[j] = packed[FR_B4 * 64 + threadIdx.x + 256 * j];
+#pragma unroll
+        for (int j = 0; j < NBF / 256; ++j)
+            sbw[threadIdx.x + 256 * j] = rr[j];
+    }
+    __syncthreads();
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
     const int col = 16 * w + r;
@@ -521,7 +536,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
         // dH3 = W4^T dZ4, dZ3 = dH3 * GELU'(z3)
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const f32x4 a = mfma(packed[(FR_B4 + t) * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+            const f32x4 a = mfma(sbw[t * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 dz[t][e] = a[e] * gelu_grad(z[t][e]);
@@ -571,7 +586,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                 f32x4 a{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    a = mfma(packed[(frB + t * 4 + q) * 64 + lane], op[q], a);
+                    a = mfma(sbw[(frB - FR_B4 + t * 4 + q) * 64 + lane], op[q], a);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     dz[t][e] = a[e] * gelu_grad(z[t][e]);
