@@ -15,9 +15,9 @@
 // and the weights are stored ("packed") with the same permutation, so the
 // activations never leave the registers between layers.
 //
-// Inference batches of up to a few tiles per SIMD use a variant in which
-// four waves share a tile's hidden layers (k_mlp_forward_split), which
-// spreads the GELU work over more waves.
+// Batches of up to a few tiles per SIMD use a variant in which four waves
+// share a tile's hidden layers (k_mlp_forward_split), which spreads the
+// GELU work over more waves.
 //
 // Weight gradients dW = dZ^T A sum over samples, a different operand
 // layout; there the workgroup stages dZ^T and A^T of its 64 samples in LDS
@@ -51,7 +51,7 @@ constexpr int BWD_CHUNK = 64;      // samples per backward workgroup pass
 constexpr int BWD_ROW = 72;        // LDS row stride (bf16): 64 samples + 8 pad
 constexpr int PART_ROWS_MAX = 128; // backward workgroups (partial-sum rows)
 constexpr int FWD_GRID_MAX = 512;  // forward workgroups (two per CU)
-constexpr int64_t SPLIT_MAX_TILES = 16384;  // largest inference batch (16-sample tiles) for the split forward
+constexpr int64_t SPLIT_MAX_TILES = 16384;  // largest batch (16-sample tiles) for the split forward
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -292,20 +292,31 @@ __global__ __launch_bounds__(256) void k_mlp_forward(float *__restrict__ y,
 // interleave on the SIMDs instead of one.
 constexpr int SPLIT_TILES = 4;
 
+template <bool TRAIN>
 __device__ inline u32x4 split_epilogue(const f32x4 &a0, const f32x4 &a1, int t0, int layer,
-                                       const float *__restrict__ sb, int g)
+                                       const float *__restrict__ sb, int g,
+                                       float *__restrict__ cache, int64_t tile, bool tv, int lane)
 {
+    f32x4 z0, z1;
     float h0[4], h1[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        h0[e] = gelu(a0[e] + sb[layer * NH + 16 * t0 + 4 * g + e]);
-        h1[e] = gelu(a1[e] + sb[layer * NH + 16 * (t0 + 1) + 4 * g + e]);
+        z0[e] = a0[e] + sb[layer * NH + 16 * t0 + 4 * g + e];
+        z1[e] = a1[e] + sb[layer * NH + 16 * (t0 + 1) + 4 * g + e];
+        h0[e] = gelu(z0[e]);
+        h1[e] = gelu(z1[e]);
+    }
+    if (TRAIN && tv) {
+        *(f32x4 *)(cache + (((tile * 3 + layer) * 8 + t0) * 256 + lane * 4)) = z0;
+        *(f32x4 *)(cache + (((tile * 3 + layer) * 8 + t0 + 1) * 256 + lane * 4)) = z1;
     }
     return u32x4{pack2(h0[0], h0[1]), pack2(h0[2], h0[3]), pack2(h1[0], h1[1]),
                  pack2(h1[2], h1[3])};
 }
 
+template <bool TRAIN>
 __global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ y,
+                                                           float *__restrict__ cache,
                                                            const float *__restrict__ x,
                                                            int64_t B,
                                                            const u32x4 *__restrict__ packed,
@@ -337,10 +348,13 @@ __global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ 
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = w >> 2, f = w & 3, r = lane & 15, g = lane >> 4;
-    const int64_t n_sets = ((B + 15) / 16 + SPLIT_TILES - 1) / SPLIT_TILES;
+    const int64_t n_tiles = (B + 15) / 16;
+    const int64_t n_sets = (n_tiles + SPLIT_TILES - 1) / SPLIT_TILES;
     const f32x4 zero{0.0f, 0.0f, 0.0f, 0.0f};
     for (int64_t set = blockIdx.x; set < n_sets; set += gridDim.x) {
-        const int64_t s = (set * SPLIT_TILES + i) * 16 + r;
+        const int64_t tile = set * SPLIT_TILES + i;
+        const bool tv = tile < n_tiles;
+        const int64_t s = tile * 16 + r;
         // layer 1: the K x N operand is x itself (features 8g..8g+7 of sample r)
         float v[8];
 #pragma unroll
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ 
         {
             const f32x4 a0 = mfma(sw[(FR_F1 + 2 * f) * 64 + lane], bx, zero);
             const f32x4 a1 = mfma(sw[(FR_F1 + 2 * f + 1) * 64 + lane], bx, zero);
-            xk[0][i][f][lane] = split_epilogue(a0, a1, 2 * f, 0, sb, g);
+            xk[0][i][f][lane] = split_epilogue<TRAIN>(a0, a1, 2 * f, 0, sb, g, cache, tile, tv, lane);
         }
         __syncthreads();
         // layers 2 and 3
@@ -369,7 +383,8 @@ __global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ 
                 a0 = mfma(fr[(8 * f + q) * 64 + lane], in[q], a0);
                 a1 = mfma(fr[(8 * f + 4 + q) * 64 + lane], in[q], a1);
             }
-            xk[layer][i][f][lane] = split_epilogue(a0, a1, 2 * f, layer, sb, g);
+            xk[layer][i][f][lane] =
+                split_epilogue<TRAIN>(a0, a1, 2 * f, layer, sb, g, cache, tile, tv, lane);
             __syncthreads();
         }
         // layer 4 (rows 0..2 of the 16-row output tile), by one wave per tile
@@ -784,11 +799,16 @@ int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_
     REQUIRE(B <= ((int64_t)1 << 34), "B too large");
     SDM_TRY
     const int64_t tiles = (B + 15) / 16;
-    if (!cache && tiles <= SPLIT_MAX_TILES) {
-        // inference up to a few tiles per SIMD: four waves per tile
+    if (tiles <= SPLIT_MAX_TILES) {
+        // up to a few tiles per SIMD: four waves per tile
         const int64_t sets = (tiles + SPLIT_TILES - 1) / SPLIT_TILES;
-        hipLaunchKernelGGL(k_mlp_forward_split, dim3((int)(sets < 256 ? sets : 256)), dim3(1024),
-                           0, stream, y, x, B, (const u32x4 *)w->packed, w->params);
+        const dim3 grid(sets < 256 ? (unsigned)sets : 256u);
+        if (cache)
+            hipLaunchKernelGGL(k_mlp_forward_split<true>, grid, dim3(1024), 0, stream, y, cache,
+                               x, B, (const u32x4 *)w->packed, w->params);
+        else
+            hipLaunchKernelGGL(k_mlp_forward_split<false>, grid, dim3(1024), 0, stream, y, cache,
+                               x, B, (const u32x4 *)w->packed, w->params);
     } else {
         // one wave per tile; inference takes two tiles at a time (larger
         // batches only), training one, writing its pre-activations

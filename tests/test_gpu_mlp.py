@@ -77,6 +77,27 @@ def test_forward_matches_bf16_oracle(sdm, ctx, B):
     assert np.array_equal(host(y), host(y2))
 
 
+
+def test_training_cache_same_in_both_forward_kernels(sdm, ctx):
+    """A batch above the split kernel's size goes through the one-wave-per-tile
+    kernel; its saved pre-activations of the first 16384 samples must equal
+    those the split kernel saves for those samples alone (the same sums)."""
+    import torch
+    th = _theta(5)
+    net = sdm.Mlp(ctx, th)
+    B_big, B_small = 300001, 16384
+    xd = dev(_x(B_big, 9))
+    y = torch.zeros((B_big, 3), dtype=torch.float32, device="cuda")
+    c_big = sdm.Mlp.cache_for(B_big)
+    c_small = sdm.Mlp.cache_for(B_small)
+    ctx.mlp_forward(y, xd, net, cache=c_big)
+    y_small = torch.zeros((B_small, 3), dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(y_small, xd[:B_small].contiguous(), net, cache=c_small)
+    _sync()
+    n = c_small.numel()
+    assert np.array_equal(host(c_big[:n]), host(c_small))
+    assert np.array_equal(host(y[:B_small]), host(y_small))
+
 def test_zero_weights_give_output_bias(sdm, ctx):
     import torch
     th = np.zeros(mlp.N_PARAMS, np.float32)
