@@ -403,12 +403,23 @@ __global__ __launch_bounds__(1024) void k_mlp_forward_split(float *__restrict__ 
 }
 
 // ---------------------------------------------------------------- backward
+// v from another lane of the same 16-lane row (a DPP operand: no LDS trip)
+template <int CTRL>
+__device__ inline float row_lane(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a row, every lane receiving it: the butterfly
+// over lane ^ 1, ^ 2, ^ 4, ^ 8.  After the first two steps the four lanes
+// of a quad hold equal values, so the half-row mirror (lane 7 - i) stands
+// for lane ^ 4, and likewise the row mirror (15 - i) for lane ^ 8.
 __device__ inline float sum16(float v)
 {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    v += __shfl_xor(v, 8, 64);
+    v += row_lane<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += row_lane<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += row_lane<0x141>(v);  // row_half_mirror
+    v += row_lane<0x140>(v);  // row_mirror
     return v;
 }
 
@@ -504,6 +515,15 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
         const int64_t tile = chunk * 4 + w;
         const bool tv = tile < n_tiles;
         const int64_t s = tile * 16 + r;
+        f32x4 z[8], h[8], dz[8];
+        load_z(z, cache, tile, tv, 2, lane);
+        // the inputs for dW1, loaded now so that they have arrived by then
+        float xin[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * g + e;
+            xin[e] = (k < NIN && s < B) ? x[s * NIN + (k < NIN ? k : 0)] : 0.0f;
+        }
 
         // ---- layer 4: dZ4 = dy
         float d4[NOUT];
@@ -525,8 +545,6 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     bsum[w][e] = t;
             }
         }
-        f32x4 z[8], h[8], dz[8];
-        load_z(z, cache, tile, tv, 2, lane);
 #pragma unroll
         for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -564,6 +582,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
             const int offW = layer == 2 ? OFF_W3 : OFF_W2;
             const int offB = layer == 2 ? OFF_B3 : OFF_B2;
             const int frB = layer == 2 ? FR_B3 : FR_B2;
+            load_z(z, cache, tile, tv, layer - 1, lane);  // in flight while dZ is staged
             u32x4 op[4];
             to_operand(op, dz);
             stage_t(G, dz, col, g);
@@ -575,7 +594,6 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     if (r == 0)
                         bsum[w][16 * t + 4 * g + e] = v;
                 }
-            load_z(z, cache, tile, tv, layer - 1, lane);
 #pragma unroll
             for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -620,11 +638,8 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     bsum[w][16 * t + 4 * g + e] = v;
             }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = 4 * g + e;
-            const float v = (k < NIN && s < B) ? x[s * NIN + (k < NIN ? k : 0)] : 0.0f;
-            H[k * BWD_ROW + col] = (uint16_t)bf16_bits(v);
-        }
+        for (int e = 0; e < 4; ++e)
+            H[(4 * g + e) * BWD_ROW + col] = (uint16_t)bf16_bits(xin[e]);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
