@@ -272,6 +272,28 @@ __device__ __forceinline__ void apply_collision_v(const Collision &c, uint32_t s
     }
 }
 
+// Inclusive scan over the 64 lanes of a wave on DPP operands (no LDS trip):
+// Hillis-Steele within each 16-lane row (shifts by 1, 2, 4, 8; lanes with no
+// source add 0), then the last lane of row 0 into row 1 and of row 2 into
+// row 3, then the last lane of row 1 into rows 2 and 3.  Every lane of the
+// wave must be active.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_lane(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, true);
+}
+
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t v)
+{
+    v += dpp_lane<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_lane<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_lane<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_lane<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_lane<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_lane<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Workgroup reduction of the statistics into counters[8] (one atomic per
 // nonzero slot per workgroup).  `red` is LDS scratch of 5*(threads/64) words.
 template <int THREADS>
@@ -281,13 +303,10 @@ __device__ __forceinline__ void flush_stats(const Stats &st, uint64_t *counters,
     constexpr int W = THREADS / 64;
     uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            v[i] += __shfl_xor(v[i], o, 64);
-    }
+    for (int i = 0; i < 5; ++i)
+        v[i] = wave_scan_u32(v[i]);  // lane 63: the wave's sum
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int i = 0; i < 5; ++i)
             red[i * W + wid] = v[i];

@@ -203,14 +203,7 @@ __device__ __forceinline__ int upper_index(const uint32_t *tab, int n, uint32_t 
 // Inclusive scan over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, 64);
-        if (lane >= o)
-            v += t;
-    }
-    return v;
+    return wave_scan_u32(v);
 }
 
 // Exclusive scan over THREADS values held one per thread; *total gets the
@@ -222,13 +215,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
 {
     constexpr int W = THREADS / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o)
-            x += y;
-    }
+    const uint32_t x = wave_scan_u32(v);
     if (lane == 63)
         scratch[wid] = x;
     __syncthreads();
@@ -768,12 +755,9 @@ __device__ __forceinline__ void store_group_stats(const GroupArgs &a, int g, con
     const int tid = threadIdx.x;
     uint32_t v[5] = {st.pairs, st.coll, st.capped, st.zeroed, st.ge2};
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            v[i] += __shfl_xor(v[i], o, 64);
-    }
-    if ((tid & 63) == 0) {
+    for (int i = 0; i < 5; ++i)
+        v[i] = wave_scan_u32(v[i]);  // lane 63: the wave's sum
+    if ((tid & 63) == 63) {
 #pragma unroll
         for (int i = 0; i < 5; ++i)
             red[i * W + (tid >> 6)] = v[i];
