@@ -64,8 +64,9 @@ enum { SDM_STREAM_SHUFFLE = 0, SDM_STREAM_GAMMA = 1, SDM_STREAM_INIT = 2,
  *  GOLOVIN        b (v1 + v2)                      p[0] = b [1/s]
  *  GEOMETRIC      E pi (r1 + r2)^2 |w(r1) - w(r2)| p[0] = E (efficiency)
  *                 r = cbrt(0.75 v / pi) (Newton cube root, 8 IEEE steps),
- *                 w(r) = 1.19e8 r^2 (r < 40 um), 8e3 r (r < 600 um),
- *                 201 sqrt(r) otherwise [m/s]
+ *                 w(r) = 1.19e8 r^2 (r < 8e3/1.19e8 m = 67.2 um),
+ *                 8e3 r (r < (201/8e3)^2 m = 631 um), 201 sqrt(r)
+ *                 otherwise [m/s]: each law up to where it meets the next
  *  CONSTANT       p[0]
  *  MULTIPLICATIVE p[0] v1 v2
  * (Golovin, constant and multiplicative: Sec. 2.1; gravitational: Sec. 4.) */
@@ -207,7 +208,7 @@ int sdm_compute_gamma(sdm_ctx *ctx, double *pair_prob,
  * g = min(gamma, floor(xi_j/xi_k)) with gamma read from slot floor(i/2)
  * (NaN and values < 1 read as 0, >= 2^64 saturate); case 1 (xi_j - g xi_k >
  * 0): xi_j -= g xi_k, A_k += g A_j; case 2: xi_j = floor(xi_k/2),
- * xi_k -= xi_j, A_j = A_j g + A_k, A_k = A_j.  xi, attr: in/out, by SD id.
+ * xi_k -= xi_j, A_j = A_k = A_k + g A_j.  xi, attr: in/out, by SD id.
  * counters_dev: optional uint64[8]. */
 int sdm_update_attributes(sdm_ctx *ctx, uint64_t *xi, double *attr,
                           int32_t n_attr, int64_t attr_stride,

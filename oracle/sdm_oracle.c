@@ -219,13 +219,26 @@ double sdmo_cbrt(double x)
     return y;
 }
 
+/* Terminal velocity [m/s] of a drop of radius r [m]: the textbook
+ * three-regime power law, k1 r^2 (Stokes), k2 r, then k3 sqrt(r), with
+ * k1 = 1.19e8 1/(m s), k2 = 8e3 1/s, k3 = 201 m^0.5/s.  The paper names the
+ * gravitational kernel's terminal velocity only as a parametric form
+ * (Sec. 4); the reading here switches law where the adjacent laws meet,
+ * r = k2/k1 (67.2 um) and r = (k3/k2)^2 (631 um), so that w(r) is
+ * continuous and increasing. */
+#define SDMO_VT_K1 1.19e8
+#define SDMO_VT_K2 8.0e3
+#define SDMO_VT_K3 201.0
+
 double sdmo_terminal_velocity(double r)
 {
-    if (r < 40.0e-6)
-        return 1.19e8 * (r * r);
-    if (r < 600.0e-6)
-        return 8.0e3 * r;
-    return 201.0 * sqrt(r);
+    const double r12 = SDMO_VT_K2 / SDMO_VT_K1;
+    const double r23 = (SDMO_VT_K3 / SDMO_VT_K2) * (SDMO_VT_K3 / SDMO_VT_K2);
+    if (r < r12)
+        return SDMO_VT_K1 * (r * r);
+    if (r < r23)
+        return SDMO_VT_K2 * r;
+    return SDMO_VT_K3 * sqrt(r);
 }
 
 double sdmo_kernel_value(int32_t kernel_id, const double *kparams,
@@ -320,59 +333,67 @@ static uint64_t gamma_count(double g)
     return (uint64_t)g;
 }
 
-/* update_attributes: eq. (4) caps gamma at floor(xi_j/xi_k) with xi_j the
- * larger multiplicity (on a tie, j is the earlier sorted position, as in the
- * CPU listing's strict comparison); case 1 of eq. (5) when xi_j - g xi_k > 0,
- * otherwise the equal-multiplicity split of eq. (6). */
+/* update_attributes (Step 3), eqs. (4)-(6), for every pair (a, b) opened at
+ * a flagged position i.  Of the two SDs, j has the larger multiplicity and
+ * k the smaller (on equal multiplicities j is the one at the earlier
+ * position).  Eq. (4): the number of collision events is
+ * gt = min(gamma, floor(xi_j / xi_k)).  With gt > 0:
+ *   eq. (5), gt xi_k < xi_j:  xi_j <- xi_j - gt xi_k,  A_k <- A_k + gt A_j;
+ *   eq. (6), gt xi_k = xi_j:  xi_j <- floor(xi_k / 2),
+ *                             xi_k <- xi_k - floor(xi_k / 2),
+ *                             A_j, A_k <- A_k + gt A_j.
+ * xi_j and A_j are unchanged in eq. (5), and xi_k, which never changes in
+ * eq. (5), is split in eq. (6).  Counters: pairs visited, pairs with gt > 0,
+ * pairs with gt < gamma, SDs whose multiplicity became 0, pairs with
+ * gamma >= 2. */
 void sdmo_update_attributes(uint64_t *xi, double *attr, int32_t n_attr,
                             int64_t attr_stride, const double *gamma,
                             const uint8_t *flag, const uint32_t *idx,
                             int64_t n_live, uint64_t *counters)
 {
     int64_t i;
-    int32_t a;
+    int32_t r;
     for (i = 0; i < n_live; ++i) {
-        uint32_t j, k;
-        uint64_t G, ratio, g, d;
+        uint32_t a, b, j, k;
+        uint64_t events, cap, gt;
         if (!flag[i])
             continue;
-        j = idx[i];
-        k = idx[i + 1];
-        if (xi[j] < xi[k]) {
-            uint32_t t = j;
-            j = k;
-            k = t;
-        }
+        a = idx[i];
+        b = idx[i + 1];
+        j = xi[a] >= xi[b] ? a : b;
+        k = j == a ? b : a;
         counters[SDMO_CNT_PAIRS] += 1;
         if (xi[k] == 0)
-            continue;
-        G = gamma_count(gamma[i / 2]);
-        ratio = xi[j] / xi[k];
-        g = G < ratio ? G : ratio;
-        if (G >= 2)
+            continue; /* an SD already removed: nothing to collide with */
+        events = gamma_count(gamma[i / 2]);
+        cap = xi[j] / xi[k]; /* floor(xi_j / xi_k), exact in integers */
+        gt = events < cap ? events : cap; /* eq. (4) */
+        if (events >= 2)
             counters[SDMO_CNT_GAMMA_GE2] += 1;
-        if (g < G)
+        if (gt < events)
             counters[SDMO_CNT_CAPPED] += 1;
-        if (g == 0)
+        if (gt == 0)
             continue;
         counters[SDMO_CNT_COLLISIONS] += 1;
-        d = xi[j] - g * xi[k];
-        if (d > 0) {
-            xi[j] = d;
-            for (a = 0; a < n_attr; ++a) {
-                double *A = attr + (int64_t)a * attr_stride;
-                A[k] = A[k] + (double)g * A[j];
+        if (gt * xi[k] < xi[j]) {
+            /* eq. (5) */
+            xi[j] = xi[j] - gt * xi[k];
+            for (r = 0; r < n_attr; ++r) {
+                double *A = attr + (int64_t)r * attr_stride;
+                A[k] = A[k] + (double)gt * A[j];
             }
         } else {
-            uint64_t h = xi[k] / 2;
-            xi[j] = h;
-            xi[k] = xi[k] - h;
-            if (h == 0)
+            /* eq. (6) */
+            uint64_t half = xi[k] / 2;
+            xi[j] = half;
+            xi[k] = xi[k] - half;
+            if (half == 0)
                 counters[SDMO_CNT_ZEROED] += 1;
-            for (a = 0; a < n_attr; ++a) {
-                double *A = attr + (int64_t)a * attr_stride;
-                A[j] = A[j] * (double)g + A[k];
-                A[k] = A[j];
+            for (r = 0; r < n_attr; ++r) {
+                double *A = attr + (int64_t)r * attr_stride;
+                double merged = A[k] + (double)gt * A[j];
+                A[j] = merged;
+                A[k] = merged;
             }
         }
     }

@@ -107,14 +107,23 @@ __device__ __forceinline__ double cbrt_newton(double x)
     return y;
 }
 
-// Three-regime power-law terminal velocity [m/s] of a drop of radius r [m].
+// Terminal velocity [m/s] of a drop of radius r [m]: three power laws,
+// k1 r^2, k2 r and k3 sqrt(r) (k1 = 1.19e8 1/(m s), k2 = 8e3 1/s,
+// k3 = 201 m^0.5/s), each used up to the radius where it meets the next one
+// (k2/k1 = 67.2 um and (k3/k2)^2 = 631 um), so that w is continuous.
+constexpr double VT_K1 = 1.19e8;
+constexpr double VT_K2 = 8.0e3;
+constexpr double VT_K3 = 201.0;
+
 __device__ __forceinline__ double terminal_velocity(double r)
 {
-    if (r < 40.0e-6)
-        return 1.19e8 * (r * r);
-    if (r < 600.0e-6)
-        return 8.0e3 * r;
-    return 201.0 * sqrt(r);
+    constexpr double r12 = VT_K2 / VT_K1;
+    constexpr double r23 = (VT_K3 / VT_K2) * (VT_K3 / VT_K2);
+    if (r < r12)
+        return VT_K1 * (r * r);
+    if (r < r23)
+        return VT_K2 * r;
+    return VT_K3 * sqrt(r);
 }
 
 __device__ __forceinline__ double kernel_value(const KernelDesc &k, double v1,
@@ -216,17 +225,15 @@ __device__ __forceinline__ Collision collide(uint64_t xa, uint64_t xb, double ga
     return c;
 }
 
-// Attribute update of eqs. (5)/(6) for one attribute row.
+// Attribute update for one attribute row: eq. (5) adds g A_j to A_k; in
+// eq. (6) both SDs take that sum.
 __device__ __forceinline__ void collide_attr(double &Aj, double &Ak, uint64_t g,
                                              bool split)
 {
-    const double gd = (double)g;
-    if (!split) {
-        Ak = Ak + gd * Aj;
-    } else {
-        Aj = Aj * gd + Ak;
-        Ak = Aj;
-    }
+    const double merged = Ak + (double)g * Aj;
+    Ak = merged;
+    if (split)
+        Aj = merged;
 }
 
 // Writes the outcome of a pair with g > 0 to the global state.

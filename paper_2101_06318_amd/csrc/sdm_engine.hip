@@ -831,15 +831,16 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
         const uint32_t cs = T.cs[bl], ce = cs + T.n[bl];
         const uint32_t ic = r - cs;
         if (((ic & 1u) == 0u) && (r + 1 < ce) && f + 1 < tot)
-            opl[w++] = f | ((uint32_t)bl << 16);
+            opl[w++] = f;  // a full 32-bit position: groups here may exceed 2^16 records
     }
     __syncthreads();
     // 2. pairs, two consecutive openers per thread so that slots 2u, 2u+1
-    //    share one Philox block when they are adjacent
+    //    share one Philox block when they are adjacent; an opener's bucket
+    //    is found again from its position
     uint32_t shift = 0;
     if (n_op) {
-        const uint32_t e0 = opl[0];
-        const uint32_t fa = e0 & 0xFFFFu, b = e0 >> 16;
+        const uint32_t fa = opl[0];
+        const int b = upper_index(T.off, nb, fa);
         shift = ((rank0 + fa - T.pc[b].slot_base) >> 1) & 1u;
     }
     for (uint32_t j = tid; 2 * j < n_op + shift; j += THREADS) {
@@ -856,9 +857,8 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             valid[u] = k >= 0 && k < (int)n_op;
             if (!valid[u])
                 continue;
-            const uint32_t e = opl[k];
-            const uint32_t f = e & 0xFFFFu;
-            bv[u] = e >> 16;
+            const uint32_t f = opl[k];
+            bv[u] = (uint32_t)upper_index(T.off, nb, f);
             const PairCtx &pc = T.pc[bv[u]];
             runv[u] = pc.run;
             qv[u] = (rank0 + f - pc.slot_base) >> 1;

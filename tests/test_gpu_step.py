@@ -10,6 +10,7 @@ import pytest
 import oracle
 from paper_2101_06318_amd import workloads
 from tests.gpu_util import dev, host
+from tests.parity import compare_step, slot_probabilities
 
 pytestmark = pytest.mark.gpu
 
@@ -28,25 +29,27 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def _check(st, ref, n_sd, what=""):
+def _gpu_result(st):
     n = int(host(st.n_live)[0])
-    assert n == ref["n_live"], what
-    assert np.array_equal(host(st.xi), ref["xi"]), what
-    got_attr = host(st.attr)
-    if not np.array_equal(got_attr, ref["attr"]):
-        rel = np.abs(got_attr - ref["attr"]) / np.maximum(np.abs(ref["attr"]), 1e-300)
-        assert rel.max() <= 1e-12, (what, rel.max())
-        raise AssertionError("attributes differ (within 1e-12) but bits differ: %s" % what)
-    assert np.array_equal(host(st.idx, np.uint32)[:n], ref["idx"][:n]), what
-    assert np.array_equal(host(st.cell_start, np.uint32), ref["cell_start"]), what
+    out = dict(n_live=n, xi=host(st.xi).copy(), attr=host(st.attr).copy(),
+               idx=host(st.idx, np.uint32).copy(), cell_start=host(st.cell_start, np.uint32))
     if st.gamma_out is not None:
-        g, rg = host(st.gamma_out), ref["gamma"]
-        bad = np.nonzero(g != rg)[0]
-        assert bad.size == 0, (what, bad[:5], g[bad[:5]], rg[bad[:5]])
+        out["gamma"] = host(st.gamma_out).copy()
+    return out
+
+
+def _check(st, ref, n_sd, what="", pre=None):
+    """Element-by-element comparison of one step; gamma mismatches are
+    classified (threshold flips are counted, anything else fails).  Returns
+    the number of flips."""
+    got = _gpu_result(st)
+    flips = compare_step(got, ref, pre, what)
+    assert np.array_equal(got["cell_start"], ref["cell_start"]), what
+    return flips
 
 
 def _run_pair(sdm, ctx, w, steps, seed, kparams=None, gamma=True, reassign=False, cell_id=None,
-              dead=None, run=0):
+              dead=None, run=0, dv_scalar=False):
     n_sd = w["n_sd"]
     kp = kparams if kparams is not None else w["kparams"]
     xi = w["xi"].copy()
@@ -61,19 +64,36 @@ def _run_pair(sdm, ctx, w, steps, seed, kparams=None, gamma=True, reassign=False
     ref["n_live"] = n_sd
     cnt = np.zeros(8, np.uint64)
     cur_cid = cid
+    total_flips = 0
     for t in range(steps):
         if reassign:
             cur_cid = oracle.reassign(n_sd, n_cell, seed, t)
             ctx.reassign(st.cell_id, n_sd, n_cell, sdm.rng(seed, 0, t))
         ctx.step(st, w["dt"], k, sdm.rng(seed, run, t), dv_per_cell=dv)
-        ref = oracle.step(ref["xi"], ref["attr"], cur_cid if n_cell > 1 else None, n_cell, w["dv"],
-                          ref["idx"], ref["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
+        prev = ref
+        step_cid = cur_cid if n_cell > 1 else None
+        ref = oracle.step(prev["xi"], prev["attr"], step_cid, n_cell, w["dv"],
+                          prev["idx"], prev["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
                           kparams=kp, seed=seed, run=run, step=t, counters=cnt,
                           want_gamma=gamma)
         cnt = ref["counters"]
         _sync()
-        _check(st, ref, n_sd, "step %d" % t)
-    assert np.array_equal(host(st.counters), cnt)
+
+        def pre(prev=prev, step_cid=step_cid, t=t):
+            return slot_probabilities(prev["xi"], prev["attr"], step_cid, n_cell, w["dv"],
+                                      prev["idx"], prev["n_live"], dt=w["dt"],
+                                      kernel_id=w["kernel_id"], kparams=kp, seed=seed,
+                                      run=run, step=t)
+        flips = _check(st, ref, n_sd, "step %d" % t, pre=pre)
+        if flips:
+            # a flipped pair: the trajectories continue from the GPU's state
+            got = _gpu_result(st)
+            ref = dict(ref, xi=got["xi"], attr=got["attr"])
+            total_flips += flips
+    if total_flips:
+        print("gamma threshold flips: %d" % total_flips)
+    else:
+        assert np.array_equal(host(st.counters), cnt)
     return st, ref
 
 
@@ -284,4 +304,19 @@ def test_largest_single_plan_and_the_limit(sdm):
     st = sdm.State(big["xi"], big["attr"], None, 1)
     with pytest.raises(sdm.SdmError):
         ctx.step(st, 1.0, sdm.kernel(0, [1500.0]), sdm.rng(6, 0, 0), dv=1e6)
+    ctx.close()
+
+
+def test_cell_beyond_2_16_records_in_a_multi_cell_plan(sdm):
+    """A 256-cell plan sized for about 300 SDs per cell, with 70 000 of the
+    SDs in one cell: that cell's single bucket holds more than 2^16 records,
+    so its group is sorted in global memory and its opener positions need
+    all 32 bits.  Two steps against the oracle, element by element."""
+    n_sd, n_cell, big = 78000, 256, 70000
+    w = workloads.box(n_sd, seed=12)
+    cid = np.random.default_rng(12).integers(0, n_cell, n_sd).astype(np.int32)
+    cid[np.random.default_rng(13).permutation(n_sd)[:big]] = 37
+    w = dict(w, n_cell=n_cell, cell_id=cid, dv=np.full(n_cell, w["dv"][0] / n_cell))
+    ctx = sdm.Context(n_sd, n_cell, 1)
+    _run_pair(sdm, ctx, w, 2, seed=12, kparams=[1500.0 * 50])
     ctx.close()

@@ -39,19 +39,49 @@ def test_kernel_values(oracle_mod):
 def test_geometric_kernel_properties(oracle_mod):
     v = 4.0 / 3.0 * np.pi * (20e-6) ** 3
     assert oracle_mod.kernel_value(1, [1.0], v, v) == 0.0      # equal fall speeds
-    # terminal velocity is increasing within each regime and positive
-    rs = np.concatenate([np.linspace(1e-6, 39e-6, 20), np.linspace(41e-6, 590e-6, 20),
-                         np.linspace(610e-6, 3e-3, 20)])
-    w = np.array([oracle_mod.terminal_velocity(r) for r in rs])
-    assert np.all(w > 0) and np.all(np.diff(w[:20]) > 0) and np.all(np.diff(w[20:40]) > 0)
-    # Stokes regime: w = k1 r^2 with k1 = 1.19e8 /m/s (10 um -> 1.19 cm/s)
-    assert abs(oracle_mod.terminal_velocity(10e-6) - 1.19e-2) < 1e-15
     # larger drop falls faster: kernel grows with the size contrast
     a1 = oracle_mod.kernel_value(1, [1.0], v, 2 * v)
     a2 = oracle_mod.kernel_value(1, [1.0], v, 8 * v)
     assert a2 > a1 > 0
     # efficiency scales the kernel linearly
     assert oracle_mod.kernel_value(1, [0.5], v, 8 * v) == a2 * 0.5
+    # pi (r1 + r2)^2 |w1 - w2| written out for one pair, r from the volume
+    r1, r2 = 15e-6, 150e-6
+    v1, v2 = 4.0 / 3.0 * np.pi * r1 ** 3, 4.0 / 3.0 * np.pi * r2 ** 3
+    want = np.pi * (r1 + r2) ** 2 * abs(1.19e8 * r1 ** 2 - 8e3 * r2)
+    assert abs(oracle_mod.kernel_value(1, [1.0], v1, v2) - want) <= 1e-12 * want
+
+
+K1, K2, K3 = 1.19e8, 8.0e3, 201.0   # textbook power-law coefficients [1/(m s), 1/s, m^0.5/s]
+
+
+def test_terminal_velocity_laws():
+    """The three laws with their textbook coefficients, each inside its own
+    range: Stokes k1 r^2, linear k2 r, square-root k3 sqrt(r)."""
+    import oracle
+    tv = oracle.terminal_velocity
+    assert abs(tv(10e-6) - 1.19e-2) <= 1e-15                 # 10 um: 1.19 cm/s
+    assert abs(tv(30e-6) - K1 * 30e-6 ** 2) <= 1e-15
+    assert abs(tv(100e-6) - 0.8) <= 1e-15                    # 100 um: 0.8 m/s
+    assert abs(tv(400e-6) - K2 * 400e-6) <= 1e-15
+    assert abs(tv(1e-3) - K3 * np.sqrt(1e-3)) <= 1e-15       # 1 mm: 6.36 m/s
+    assert abs(tv(2e-3) - K3 * np.sqrt(2e-3)) <= 1e-15
+
+
+def test_terminal_velocity_continuous_at_the_regime_changes():
+    """The law changes where the neighbouring laws meet (r = k2/k1 and
+    r = (k3/k2)^2), so w(r) has no jump there and increases throughout."""
+    import oracle
+    tv = oracle.terminal_velocity
+    for rb in (K2 / K1, (K3 / K2) ** 2):
+        lo, hi = tv(np.nextafter(rb, 0.0)), tv(rb)
+        assert abs(hi - lo) <= 1e-14 * hi, (rb, lo, hi)
+        # within 0.1 % of the boundary w moves by at most 0.3 %
+        assert abs(tv(rb * 0.999) - tv(rb * 1.001)) < 0.003 * tv(rb)
+    assert abs(K2 / K1 - 67.2269e-6) < 1e-10 and abs((K3 / K2) ** 2 - 631.2656e-6) < 1e-10
+    rs = np.geomspace(1e-6, 5e-3, 4000)
+    w = np.array([tv(r) for r in rs])
+    assert np.all(w > 0) and np.all(np.diff(w) > 0)
 
 
 def test_moments_definition(oracle_mod):
