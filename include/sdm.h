@@ -135,6 +135,28 @@ int sdm_urand(sdm_ctx *ctx, double *u01, int64_t n, const sdm_rng *rng,
 int sdm_remove_if_equal_0(sdm_ctx *ctx, uint32_t *idx, int64_t *n_live_dev,
                           const uint64_t *xi, hipStream_t stream);
 
+/* Largest Index sdm_remove_if_equal_0_noalloc accepts (4,194,304 ids). */
+#define SDM_NOALLOC_MAX_IDS ((int64_t)1 << 22)
+
+/* Step 0 for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops or harnesses that forbid hipMalloc): the
+ * same result as sdm_remove_if_equal_0, with no context and no allocation
+ * of any kind.  Its scratch is one fixed library-owned device array of
+ * SDM_NOALLOC_MAX_IDS + 64 ids and 2112 tile counts (16 MiB + 8.3 KiB),
+ * which every GPU the library runs on holds until the process ends; its
+ * address is resolved once per device on the first call (with that device
+ * current).  All calls on one GPU share that array and it keeps the last
+ * call's contents (nothing in it needs to start at zero), so calls that
+ * overlap on one GPU (two streams, two host threads) race: serialise them.
+ * idx: device uint32[n_sd_max], in/out; n_live_dev: device int64, in/out,
+ * at most n_sd_max (a larger value is read as n_sd_max); xi: device uint64
+ * by SD id.  The current device must be the device of idx and stream.
+ * Errors: SDM_E_INVALID for a null pointer or n_sd_max outside
+ * [1, SDM_NOALLOC_MAX_IDS]; SDM_E_HIP if the scratch address cannot be
+ * resolved or a launch fails. */
+int sdm_remove_if_equal_0_noalloc(uint32_t *idx, int64_t *n_live_dev, const uint64_t *xi,
+                                  int64_t n_sd_max, hipStream_t stream);
+
 /* --------------------------------------------------- Step 1 (R3, R4) */
 /* Stable counting sort of idx[0:n_live] by cell_id[idx[i]] (the Index's
  * sort-by-key on the cell id, Sec. 3.1).

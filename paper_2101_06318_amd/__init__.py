@@ -87,6 +87,7 @@ SIGNATURES = {
     "sdm_set_plan_limits": (_INT, [_P, _I32, _I32]),
     "sdm_urand": (_INT, [_P, _P, _I64, C.POINTER(Rng), _U32, _P]),
     "sdm_remove_if_equal_0": (_INT, [_P, _P, _P, _P, _P]),
+    "sdm_remove_if_equal_0_noalloc": (_INT, [_P, _P, _P, _I64, _P]),
     "sdm_cell_sort": (_INT, [_P, _P, _P, _P, _P, _I32, _P]),
     "sdm_shuffle_per_cell": (_INT, [_P, _P, _P, _P, _P, _P, _I32, _P, C.POINTER(Rng), _P]),
     "sdm_flag_pairs": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P]),
@@ -179,6 +180,17 @@ def rng(seed, run=0, step=0, step_dev=None):
     r.seed, r.run, r.step = int(seed), int(run), int(step)
     r.step_dev = _ptr(step_dev)
     return r
+
+
+NOALLOC_MAX_IDS = 1 << 22
+
+
+def remove_if_equal_0_noalloc(idx, n_live, xi, n_sd_max=None, stream=None):
+    """Step 0 without a context or any allocation (the library's fixed
+    scratch); n_sd_max defaults to idx's length."""
+    cap = int(idx.numel()) if n_sd_max is None else int(n_sd_max)
+    _check(lib().sdm_remove_if_equal_0_noalloc(_ptr(idx), _ptr(n_live), _ptr(xi), cap,
+                                               _stream(stream)))
 
 
 class Context:

@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sdm_internal.h"
 
@@ -38,14 +39,14 @@ constexpr int CMP_THREADS = 256;
 constexpr int CMP_EPT = 8;
 constexpr int CMP_TILE = CMP_THREADS * CMP_EPT;
 
-__global__ void k_compact_count(const uint32_t *idx, const int64_t *n_live,
+__global__ void k_compact_count(const uint32_t *idx, const int64_t *n_live, int64_t cap,
                                 const uint64_t *xi, uint32_t *tile_cnt)
 {
     __shared__ uint32_t s;
     if (threadIdx.x == 0)
         s = 0;
     __syncthreads();
-    const int64_t n = *n_live;
+    const int64_t n = min(*n_live, cap);
     const int64_t base = (int64_t)blockIdx.x * CMP_TILE;
     uint32_t c = 0;
     for (int k = 0; k < CMP_EPT; ++k) {
@@ -59,7 +60,7 @@ __global__ void k_compact_count(const uint32_t *idx, const int64_t *n_live,
         tile_cnt[blockIdx.x] = s;
 }
 
-__global__ void k_compact_scan(uint32_t *tile_cnt, int n_tiles, int64_t *n_live)
+__global__ void k_compact_scan(uint32_t *tile_cnt, int n_tiles, int64_t *n_live, int64_t cap)
 {
     // single block: exclusive scan of the tile counts (serial per chunk)
     __shared__ uint32_t part[TPB + 1];
@@ -88,7 +89,7 @@ __global__ void k_compact_scan(uint32_t *tile_cnt, int n_tiles, int64_t *n_live)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        tile_cnt[n_tiles] = *n_live;  // old count, for the copy-back bound
+        tile_cnt[n_tiles] = (uint32_t)min(*n_live, cap);  // old count, read by the scatter
         *n_live = (int64_t)part[TPB];
     }
 }
@@ -297,6 +298,63 @@ __global__ void k_reassign(int32_t *cell_id, int64_t n_sd, int32_t n_cell, uint6
 }  // namespace
 
 // ====================================================================== ABI
+// Step 0 as four launches over an Index of capacity cap: per-tile live
+// counts, their scan (which also updates *n_live), the stable scatter into
+// tmp, and the copy back.  tmp holds cap + 64 ids, tile_cnt
+// blocks_for(cap, CMP_TILE) + 1 words.
+static void launch_compaction(uint32_t *idx, int64_t *n_live, int64_t cap, const uint64_t *xi,
+                              uint32_t *tmp, uint32_t *tile_cnt, hipStream_t stream)
+{
+    const int n_tiles = blocks_for(cap, CMP_TILE);
+    hipLaunchKernelGGL(k_compact_count, dim3(n_tiles), dim3(CMP_THREADS), 0, stream, idx,
+                       n_live, cap, xi, tile_cnt);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(TPB), 0, stream, tile_cnt, n_tiles, n_live,
+                       cap);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(n_tiles), dim3(CMP_THREADS), 0, stream, idx,
+                       tile_cnt, n_tiles, xi, tmp);
+    hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(cap, TPB)), dim3(TPB), 0, stream, idx, tmp,
+                       n_live);
+    SDM_HIP(hipGetLastError());
+}
+
+// Fixed scratch of sdm_remove_if_equal_0_noalloc, for callers that cannot
+// allocate: the compacted ids (SDM_NOALLOC_MAX_IDS + 64 words), then the
+// per-tile counts.  Every GPU the library runs on holds its own copy for the
+// life of the process.  In host code `scratch` names a host-side stand-in,
+// never the device memory: kernels receive the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int64_t NOALLOC_IDS_WORDS = SDM_NOALLOC_MAX_IDS + 64;
+constexpr int64_t NOALLOC_TILE_WORDS = (SDM_NOALLOC_MAX_IDS + CMP_TILE - 1) / CMP_TILE + 64;
+static __device__ __align__(256) uint32_t scratch[NOALLOC_IDS_WORDS + NOALLOC_TILE_WORDS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static uint32_t *g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device, resolved once per
+// device with that device current.
+static int noalloc_scratch(uint32_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(SDM_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(SDM_E_UNSUPPORTED, "device %d beyond the %d the scratch table covers", dev,
+                    NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SDM_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SDM_OK;
+}
+
 static int check_kernel(const sdm_kernel *k)
 {
     if (!k)
@@ -339,15 +397,23 @@ int sdm_remove_if_equal_0(sdm_ctx *ctx, uint32_t *idx, int64_t *n_live_dev, cons
     REQUIRE(ctx && idx && n_live_dev && xi, "null argument");
     SDM_TRY
     const int n_tiles = blocks_for(ctx->n_sd_max, CMP_TILE);
-    hipLaunchKernelGGL(k_compact_count, dim3(n_tiles), dim3(CMP_THREADS), 0, stream, idx,
-                       n_live_dev, xi, ctx->tile_cnt);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(TPB), 0, stream, ctx->tile_cnt, n_tiles,
-                       n_live_dev);
-    hipLaunchKernelGGL(k_compact_scatter, dim3(n_tiles), dim3(CMP_THREADS), 0, stream, idx,
-                       ctx->tile_cnt, n_tiles, xi, ctx->tmp_u32);
-    hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(ctx->n_sd_max, TPB)), dim3(TPB), 0, stream,
-                       idx, ctx->tmp_u32, n_live_dev);
-    SDM_HIP(hipGetLastError());
+    launch_compaction(idx, n_live_dev, ctx->n_sd_max, xi, ctx->tmp_u32, ctx->tile_cnt, stream);
+    SDM_CATCH
+}
+
+int sdm_remove_if_equal_0_noalloc(uint32_t *idx, int64_t *n_live_dev, const uint64_t *xi,
+                                  int64_t n_sd_max, hipStream_t stream)
+{
+    REQUIRE(idx && n_live_dev && xi, "null argument");
+    REQUIRE(n_sd_max >= 1 && n_sd_max <= SDM_NOALLOC_MAX_IDS,
+            "n_sd_max = %lld outside [1, %lld] (the fixed scratch holds SDM_NOALLOC_MAX_IDS ids)",
+            (long long)n_sd_max, (long long)SDM_NOALLOC_MAX_IDS);
+    uint32_t *ws = nullptr;
+    const int rc = noalloc_scratch(&ws);
+    if (rc != SDM_OK)
+        return rc;
+    SDM_TRY
+    launch_compaction(idx, n_live_dev, n_sd_max, xi, ws, ws + NOALLOC_IDS_WORDS, stream);
     SDM_CATCH
 }
 
