@@ -149,6 +149,97 @@ __device__ __forceinline__ double kernel_value(const KernelDesc &k, double v1,
     }
 }
 
+// ------------------------------------------------- pair-rate upper bounds
+// A pair collides only if its gamma = ceil(p - phi) is at least 1, i.e. only
+// if p > phi.  With nonnegative factors, p >= 0 and phi < 1, so a pair whose
+// upper bound P >= p is below phi has p - phi in (-1, 0) and gamma = -0.0
+// exactly: no collision, nothing to read or write.  The bound is built from
+// per-SD codes that the tile kernel packs into each record:
+//  * volume code (13 bits): the IEEE pattern of v >= 0 read as an integer is
+//    monotone in v; rounded up to a multiple of 2^50 (two mantissa bits
+//    kept) it decodes to a double in [v, 1.25 v].  +inf, NaN and negative v
+//    (sign bit set) give codes that decode to +inf or NaN;
+//  * multiplicity code (8 bits): the same on (double)xi, relative to 1.0;
+//    255 decodes to +inf.
+// P evaluates each kernel in its own operation order with the decoded
+// bounds (every step is monotone for nonnegative operands under round to
+// nearest), times 1 + 2^-9, which also covers the gravitational kernel's
+// cube root and terminal velocity taken in single precision there.  A NaN
+// or infinite P never rules a pair out.
+constexpr uint32_t VCODE_INF = 8191u;
+constexpr uint32_t XCODE_INF = 255u;
+
+__device__ __forceinline__ uint32_t vcode_up(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    if (u >= 0x7FF0000000000000ull)  // +inf, NaN, negative (and -0.0)
+        return VCODE_INF;
+    return (uint32_t)((u + ((1ull << 50) - 1ull)) >> 50);
+}
+
+__device__ __forceinline__ double vcode_decode(uint32_t c)
+{
+    return __longlong_as_double((long long)((uint64_t)c << 50));
+}
+
+__device__ __forceinline__ uint32_t xcode_up(uint64_t xi)  // xi >= 1
+{
+    const uint64_t u = (uint64_t)__double_as_longlong((double)xi) - 0x3FF0000000000000ull;
+    const uint64_t c = (u + ((1ull << 50) - 1ull)) >> 50;
+    return c < XCODE_INF ? (uint32_t)c : XCODE_INF;
+}
+
+__device__ __forceinline__ double xcode_decode(uint32_t c)
+{
+    return c >= XCODE_INF ? __longlong_as_double(0x7FF0000000000000ll)
+                          : __longlong_as_double((long long)(0x3FF0000000000000ull +
+                                                             ((uint64_t)c << 50)));
+}
+
+// Upper bound of cbrt(x) for x >= 0: x rounded up to single precision
+// (normal range), cube root as exp2(log2(x)/3) in single precision (error
+// below 1e-5 relative), then raised by 2^-10.
+__device__ __forceinline__ double cbrt_upper(double x)
+{
+    if (!(x > 0.0))
+        return x == 0.0 ? 0.0 : x;  // 0, or NaN propagates
+    if (!(x < 3.0e38))
+        return __longlong_as_double(0x7FF0000000000000ll);  // beyond float: no bound
+    float xf = (float)x;
+    if ((double)xf < x)
+        xf = __uint_as_float(__float_as_uint(xf) + 1u);
+    xf = fmaxf(xf, 1.17549435e-38f);
+    const float y = exp2f(log2f(xf) * (1.0f / 3.0f));
+    return (double)y * (1.0 + 0x1p-10);
+}
+
+__device__ __forceinline__ double kernel_bound(int32_t kid, double kp, double V1, double V2)
+{
+    switch (kid) {
+    case KERNEL_GOLOVIN:
+        return kp * (V1 + V2);
+    case KERNEL_GEOMETRIC: {
+        const double R1 = cbrt_upper((0.75 * V1) / SDM_PI_D);
+        const double R2 = cbrt_upper((0.75 * V2) / SDM_PI_D);
+        const double W = fmax(terminal_velocity(R1), terminal_velocity(R2));
+        const double rs = R1 + R2;
+        return ((SDM_PI_D * (rs * rs)) * W) * kp;
+    }
+    case KERNEL_CONSTANT:
+        return kp;
+    case KERNEL_MULTIPLICATIVE:
+        return kp * (V1 * V2);
+    default:
+        return __longlong_as_double(0x7FF8000000000000ll);
+    }
+}
+
+// Codes of one SD as the record carries them: xi code | volume code << 8.
+__device__ __forceinline__ uint32_t sd_codes(uint64_t xi, double v)
+{
+    return xcode_up(xi) | (vcode_up(v) << 8);
+}
+
 // F(n) = ((n^2 - n)/2) / floor(n/2): n - 1 for even n, n for odd n.
 __device__ __forceinline__ uint64_t pair_scale(uint64_t n)
 {

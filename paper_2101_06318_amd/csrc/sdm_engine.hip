@@ -82,7 +82,7 @@ struct TileArgs {
     const int32_t *seg_run;
     uint16_t *tile_off;
     RecK *rec_k;           // list modes: (key, id)
-    RecA *rec_a;           // fused mode records
+    uint64_t *rec_f;       // fused mode records (8 B, RF_* layout)
     uint32_t chunk;        // 16-B records per LDS staging pass
     uint32_t *start_zero;  // bucket_start to clear for k_colsum's sums (or null)
     uint32_t *n_acc;
@@ -102,7 +102,7 @@ struct GroupArgs {
     const int32_t *cell_bucket_base;
     const uint16_t *tile_offT;  // [B+1][n_tiles]
     const RecK *rec_k;
-    const RecA *rec_a;
+    const uint64_t *rec_f;
     const int32_t *cell_id;
     const uint32_t *bucket_start;
     uint32_t *cell_start;
@@ -547,8 +547,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                 const uint32_t b = bb + (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
                 const uint32_t r = atomicAdd(&hist[b], 1u);
                 bk[j] = b | (r << 16);
-                if (!LIST)  // the 24 key bits below the bucket's, and the bucket's low 8 bits
-                    k32[j] = ((uint32_t)(kk[e] >> (29 - h)) & 0xFFFFFFu) | (b << 24);
+                if (!LIST)  // the 24 key bits below the bucket's, and the bucket mod 32
+                    k32[j] = ((uint32_t)(kk[e] >> (29 - h)) & 0xFFFFFFu) | ((b & 31u) << 24);
             }
         }
     }
@@ -633,30 +633,32 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             vv[2 * k + 1] = v1;
         }
     }
+    // 8-B records per pass: slot in the tile, bucket mod 32, 24 key bits,
+    // the bound codes of xi and v
     uint64_t *sta = stage;
-    // 24-B records per pass, even so that every pass starts 16-B aligned
-    const uint32_t CHA = ((2 * CH) / 3) & ~1u;
-    for (uint32_t c0 = 0; c0 < total; c0 += CHA) {
+    const uint32_t CHF = 2u * CH;
+    for (uint32_t c0 = 0; c0 < total; c0 += CHF) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            if (pos[j] - c0 < CHA) {
-                const uint32_t q = 3u * (pos[j] - c0);
-                sta[q] = (uint64_t)(uint32_t)(2 * (pair0 + (int64_t)(j >> 1) * THREADS + tid) +
-                                              (j & 1)) |
-                         ((uint64_t)k32[j] << 32);
-                sta[q + 1] = xv[j];
-                sta[q + 2] = (uint64_t)__double_as_longlong(vv[j]);
+            if (pos[j] - c0 < CHF) {
+                const uint32_t local = 2u * ((uint32_t)(j >> 1) * THREADS + (uint32_t)tid) +
+                                       (uint32_t)(j & 1);
+                const uint32_t codes = sd_codes(xv[j], vv[j]);
+                sta[pos[j] - c0] = (uint64_t)local |
+                                   ((uint64_t)(k32[j] >> 24) << RF_BKT_SHIFT) |
+                                   ((uint64_t)(k32[j] & 0xFFFFFFu) << RF_KEY_SHIFT) |
+                                   ((uint64_t)codes << RF_XC_SHIFT);
             }
         }
         __syncthreads();
-        const uint32_t n3 = 3u * min(CHA, total - c0);
-        uint64_t *dst = reinterpret_cast<uint64_t *>(a.rec_a + rbase + c0);
+        const uint32_t n = min(CHF, total - c0);
+        uint64_t *dst = a.rec_f + rbase + c0;
         const uint4 *src4 = reinterpret_cast<const uint4 *>(sta);
         uint4 *dst4 = reinterpret_cast<uint4 *>(dst);
-        for (uint32_t i = tid; i < n3 / 2; i += THREADS)
+        for (uint32_t i = tid; i < n / 2; i += THREADS)
             dst4[i] = src4[i];
-        if ((n3 & 1u) && tid == 0)
-            dst[n3 - 1] = sta[n3 - 1];
+        if ((n & 1u) && tid == 0)
+            dst[n - 1] = sta[n - 1];
         __syncthreads();
     }
 }
@@ -708,6 +710,17 @@ __device__ __forceinline__ double pair_prob(const PairCtx &pc, uint64_t xa, doub
     const double ak = kernel_value(kd, va, vb);
     const uint64_t xm = xa > xb ? xa : xb;
     return (ak * (double)xm) * pc.norm;
+}
+
+// Upper bound of p from the two SDs' codes (xi code | volume code << 8);
+// +inf where the cell's factors are not all nonnegative.
+__device__ __forceinline__ double pair_bound(const PairCtx &pc, uint32_t ca, uint32_t cb)
+{
+    if (!(pc.kp >= 0.0 && pc.norm >= 0.0))
+        return __longlong_as_double(0x7FF0000000000000ll);
+    const double a = kernel_bound(pc.kid, pc.kp, vcode_decode(ca >> 8), vcode_decode(cb >> 8));
+    const double X = xcode_decode(max(ca & 255u, cb & 255u));
+    return ((a * X) * pc.norm) * (1.0 + 0x1p-9);
 }
 
 template <class Args>
@@ -973,11 +986,11 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
     // gather: tile map and the group's run in every tile; sort: (key bits,
-    // id) words by sub-bucket position; afterwards the records in sorted
-    // order (fused mode: xi and v, 16 B per record; their ids go to the
-    // sub-bucket table, dead by then)
-    __shared__ __align__(16) unsigned char pool[CAP * 16];
-    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= 16 * CAP,
+    // id) words (list modes: keys, then ids) by sub-bucket position;
+    // afterwards the fused mode's bound codes in sorted order (their ids go
+    // to the sub-bucket table, dead by then)
+    __shared__ __align__(16) unsigned char pool[CAP * 12];
+    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= 12 * CAP,
                   "run tables must fit the sort pool");
     // run_pre: the group's records before each tile's run; run_base: the
     // record slot of a group position li in tile t is run_base[t] + li
@@ -1083,8 +1096,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         // (bits 28 - h .. 52 - h) and the bucket's low 8 bits; they fix the
         // bucket and sub-bucket (u <= 24), and the rank falls back to the
         // whole key only between equal stored bits
-        uint64_t key[EPT], xv[EPT];
-        double vv[EPT];
+        uint64_t key[EPT];
+        uint32_t cod[EPT];  // fused mode: the bound codes
         uint32_t sid[EPT], sbk[EPT], fp[EPT];
         uint8_t blk[EPT], gcl[EPT];
         // every thread loads all its slots unconditionally (slots past tot
@@ -1097,11 +1110,11 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
                 const int t = tmap[li];
                 const uint32_t pos = run_base[t] + li;
-                const RecA ra = a.rec_a[pos];
-                sid[e] = (uint32_t)ra.sk;
-                key[e] = ra.sk >> 32;  // 24 key bits | bucket low 8 bits << 24
-                xv[e] = ra.xi;
-                vv[e] = ra.v;
+                const uint64_t r = a.rec_f[pos];
+                sid[e] = (uint32_t)(t_first + t) * (uint32_t)a.tile +
+                         ((uint32_t)r & ((1u << RF_BKT_SHIFT) - 1u));
+                key[e] = (r >> RF_BKT_SHIFT) & ((1ull << (RF_XC_SHIFT - RF_BKT_SHIFT)) - 1ull);
+                cod[e] = (uint32_t)(r >> RF_XC_SHIFT);
             }
         } else if (tot > 0) {
 #pragma unroll
@@ -1112,8 +1125,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 const RecK rk = a.rec_k[pos];
                 key[e] = rk.key;
                 sid[e] = rk.s;
-                xv[e] = 0;
-                vv[e] = 0.0;
+                cod[e] = 0;
             }
         }
         const uint32_t step = step_of(a.step, a.step_dev);
@@ -1127,10 +1139,10 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             if (li < tot) {
                 uint32_t bl;
                 if (fused) {
-                    // the bucket from its low 8 bits (a group spans < 256
+                    // the bucket from its low 5 bits (a group spans <= 32
                     // buckets); key[] keeps the 24 key bits
-                    bl = ((uint32_t)(key[e] >> 24) - (uint32_t)b0) & 255u;
-                    key[e] &= 0xFFFFFFu;
+                    bl = ((uint32_t)key[e] - (uint32_t)b0) & 31u;
+                    key[e] = (key[e] >> (RF_KEY_SHIFT - RF_BKT_SHIFT)) & 0xFFFFFFu;
                     gcl[e] = t_cl[bl];
                 } else {
                     // the record's cell among the group's cells
@@ -1252,9 +1264,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             return;
         }
 
-        // 3. the records in sorted order (SoA in the pool), idx, seams
-        uint64_t *RX = reinterpret_cast<uint64_t *>(pool);
-        double *RV = reinterpret_cast<double *>(pool + 8 * CAP);
+        // 3. ids and bound codes in sorted order, idx, seams
+        uint32_t *RC = reinterpret_cast<uint32_t *>(pool);
         uint32_t *RS = sub_hist;  // the sub-bucket table is dead after the ranks
         // position -> slot: the low two bits XORed with bits 4-5, so that
         // lanes reading positions 4 apart (two pairs per thread) hit
@@ -1265,8 +1276,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             if (sbk[e] == 0xFFFFFFFFu)
                 continue;
             const uint32_t f = fp[e];
-            RX[sw(f)] = xv[e];
-            RV[sw(f)] = vv[e];
+            RC[sw(f)] = cod[e];
             RS[sw(f)] = sid[e];
         }
         if (tid < 64) {
@@ -1308,9 +1318,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 if (!seam)
                     continue;
                 SeamRec rec;
-                rec.xi = RX[sw(f)];
-                rec.v = RV[sw(f)];
                 rec.s = RS[sw(f)];
+                rec.xi = a.xi[rec.s];
+                rec.v = a.attr[rec.s];
                 rec.rank = rank0 + f;
                 rec.cell = a.bucket_cell[b0 + bl];
                 rec.cs = cs;
@@ -1333,13 +1343,15 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         }
 
         // 4. pairs k = 2j, 2j + 1 per thread (adjacent pair slots share one
-        //    Philox block): eq. (3), gamma, eqs. (4)-(6)
+        //    Philox block): the bound of eq. (3) from the codes against phi;
+        //    only pairs it does not rule out read xi and the volumes from the
+        //    state for the exact eq. (3), gamma and eqs. (4)-(6)
         Stats st{0, 0, 0, 0, 0};
         const uint32_t n_pairs = t_poff[nb];
         for (uint32_t j = tid; 2 * j < n_pairs; j += THREADS) {
             uint32_t qv[2] = {0, 0}, runv[2] = {0, 0}, fv[2] = {0, 0};
             int bv[2] = {0, 0};
-            double pv[2] = {0.0, 0.0};
+            double pub[2] = {0.0, 0.0};
             bool valid[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -1354,8 +1366,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 fv[u] = f;
                 runv[u] = pc.run;
                 qv[u] = (rank0 + f - pc.slot_base) >> 1;
-                pv[u] =
-                    pair_prob(pc, RX[sw(f)], RV[sw(f)], RX[sw(f + 1)], RV[sw(f + 1)]);
+                pub[u] = pair_bound(pc, RC[sw(f)], RC[sw(f + 1)]);
             }
             double phi[2] = {0.0, 0.0};
             if (valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1u && runv[0] == runv[1]) {
@@ -1374,9 +1385,19 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             for (int u = 0; u < 2; ++u) {
                 if (!valid[u])
                     continue;
+                const PairCtx &pc = t_pc[bv[u]];
+                if (pub[u] < phi[u]) {  // gamma = -0.0: no collision
+                    st.pairs += 1;
+                    if (a.gamma_out)
+                        a.gamma_out[pc.gbase + qv[u]] = -0.0;
+                    continue;
+                }
                 const uint32_t f = fv[u];
-                finish_pair_v(a, t_pc[bv[u]], qv[u], pv[u], phi[u], RS[sw(f)], RX[sw(f)],
-                              RV[sw(f)], RS[sw(f + 1)], RX[sw(f + 1)], RV[sw(f + 1)], st);
+                const uint32_t sa = RS[sw(f)], sb2 = RS[sw(f + 1)];
+                const uint64_t xa = a.xi[sa], xb = a.xi[sb2];
+                const double va = a.attr[sa], vb = a.attr[sb2];
+                const double p = pair_prob(pc, xa, va, xb, vb);
+                finish_pair_v(a, pc, qv[u], p, phi[u], sa, xa, va, sb2, xb, vb, st);
             }
         }
         if (a.counters)
@@ -1398,7 +1419,10 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     for (uint32_t li = tid; li < tot; li += THREADS) {
         const int t = upper_index(run_pre, ntl, li);
         const uint32_t pos = run_base[t] + li;
-        const uint32_t s = fused ? (uint32_t)a.rec_a[pos].sk : a.rec_k[pos].s;
+        const uint32_t s =
+            fused ? (uint32_t)(t_first + t) * (uint32_t)a.tile +
+                        ((uint32_t)a.rec_f[pos] & ((1u << RF_BKT_SHIFT) - 1u))
+                  : a.rec_k[pos].s;
         const uint64_t k =
             fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
         a.sk[base2 + li] = k;
@@ -1678,7 +1702,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
         if (fused) {
-            p->rec_a = (RecA *)dalloc(p, sizeof(RecA) * R);
+            p->rec_f = (uint64_t *)dalloc(p, sizeof(uint64_t) * R);
         } else {
             p->rec_k = (RecK *)dalloc(p, sizeof(RecK) * R);
         }
@@ -1832,7 +1856,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.seg_run = p->seg_run;
     ta.tile_off = p->tile_off;
     ta.rec_k = p->rec_k;
-    ta.rec_a = p->rec_a;
+    ta.rec_f = p->rec_f;
     ta.chunk = p->chunk;
     ta.start_zero = p->n_tiles > 64 ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
@@ -1869,7 +1893,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_bucket_base = p->cell_bucket_base;
     ga.tile_offT = p->tile_offT;
     ga.rec_k = p->rec_k;
-    ga.rec_a = p->rec_a;
+    ga.rec_f = p->rec_f;
     ga.cell_id = in.cell_id;
     ga.bucket_start = p->bucket_start;
     ga.cell_start = cell_start;

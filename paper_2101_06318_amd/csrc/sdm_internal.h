@@ -60,20 +60,21 @@ struct HipError {
 enum EngineMode { MODE_FUSED = 0, MODE_SHUFFLE = 1, MODE_CELLSORT = 2 };
 
 // One SD's record between the tile and group kernels.  List modes: (shuffle
-// key, id).  Fused step: id in the low word; in the high word the 24 key
-// bits below the bucket's and the bucket's low 8 bits; multiplicity and
-// volume (24 B).  The group kernel draws the whole key again only for
-// records whose stored bits tie.
+// key, id), 16 B.  Fused step: one 8-B word (layout RF_* below): the SD's
+// slot within its tile, the bucket's low 5 bits, the 24 key bits below the
+// bucket's, and upper-bound codes of its multiplicity and volume.  The
+// group kernel draws the whole key again only for records whose stored
+// bits tie, and reads xi and the attributes from the state only for pairs
+// whose bound does not already rule a collision out.
 struct __attribute__((aligned(16))) RecK {
     uint64_t key;
     uint32_t s;
     uint32_t pad;
 };
-struct RecA {
-    uint64_t sk;
-    uint64_t xi;
-    double v;
-};
+constexpr int RF_BKT_SHIFT = 14;  // bits 0-13: slot within the tile (tiles <= 16384 slots)
+constexpr int RF_KEY_SHIFT = 19;  // bits 14-18: bucket mod 32 (groups span <= 32 buckets)
+constexpr int RF_XC_SHIFT = 43;   // bits 19-42: 24 key bits; bits 43-50: xi bound code
+constexpr int RF_VC_SHIFT = 51;   // bits 51-63: volume bound code
 
 // Pair that straddles two groups: the opener's record, written by the
 // group holding it and completed by the finish kernel.
@@ -120,7 +121,7 @@ struct Plan {
     uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
     // records in tile-local bucket order, [n_tiles * tile]
     RecK *rec_k = nullptr;                // list modes: (key, id)
-    RecA *rec_a = nullptr;                // fused mode records
+    uint64_t *rec_f = nullptr;            // fused mode records (8 B)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     int gept = 0;                         // records per group-kernel thread (4 or 8)
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
