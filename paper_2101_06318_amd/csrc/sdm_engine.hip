@@ -961,7 +961,7 @@ __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int
 }
 
 // --------------------------------------------------------------- k_group
-template <int THREADS, int EPT>
+template <int THREADS, int EPT, bool FUSED>
 __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
@@ -989,8 +989,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     // id) words (list modes: keys, then ids) by sub-bucket position;
     // afterwards the fused mode's bound codes in sorted order (their ids go
     // to the sub-bucket table, dead by then)
-    __shared__ __align__(16) unsigned char pool[CAP * 12];
-    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= 12 * CAP,
+    constexpr int POOL = FUSED ? 8 * CAP : 12 * CAP;
+    __shared__ __align__(16) unsigned char pool[POOL];
+    static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= POOL,
                   "run tables must fit the sort pool");
     // run_pre: the group's records before each tile's run; run_base: the
     // record slot of a group position li in tile t is run_base[t] + li
@@ -1003,7 +1004,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     const int nb = b1 - b0;
     const int nt = a.n_tiles;
     const int64_t Bp = a.B + 1;
-    const bool fused = a.mode == MODE_FUSED;
+    constexpr bool fused = FUSED;
     const uint32_t rank0 = a.bucket_start[b0];
     const uint32_t tot = a.bucket_start[b1] - rank0;
     if (tid == 0)
@@ -1928,11 +1929,17 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.group_tot = p->group_tot;
     ga.group_stats = p->group_stats;
     mark(1);
-    if (p->gept == GROUP_EPT_L)
-        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L>), dim3(p->G),
+    if (p->gept == GROUP_EPT_L && !list)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (p->gept == GROUP_EPT_L)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, false>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (!list)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     else
-        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S>), dim3(p->G),
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, false>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     SDM_HIP(hipGetLastError());
 
