@@ -257,6 +257,32 @@ __device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_
     __syncthreads();
 }
 
+// lds_exclusive_scan on 16-bit entries (every sum below 2^16).
+template <int THREADS, int PER>
+__device__ __forceinline__ void lds_exclusive_scan16(uint16_t *arr, int n, uint32_t *scratch)
+{
+    uint32_t loc[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x * PER + i;
+        loc[i] = idx < n ? arr[idx] : 0u;
+        sum += loc[i];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<THREADS>(sum, scratch, &total);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int idx = threadIdx.x * PER + i;
+        if (idx < n)
+            arr[idx] = (uint16_t)run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 0)
+        arr[n] = (uint16_t)total;
+    __syncthreads();
+}
+
 // -------------------------------------------------------------- k_colsum
 struct ScanArgs {
     const uint16_t *tile_off;
@@ -815,8 +841,6 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             ++cnt;
         } else if (opener || (f == 0 && (ic & 1u))) {
             SeamRec rec;
-            rec.xi = get.xi(f);
-            rec.v = get.v(f);
             rec.s = get.s(f);
             rec.rank = r;
             rec.cell = a.bucket_cell[b0 + bl];
@@ -961,8 +985,10 @@ __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int
 }
 
 // --------------------------------------------------------------- k_group
+// The usual fused plans (seven records per thread, 39 KB of LDS) run three
+// workgroups per CU: at most 80 VGPRs, six waves per SIMD.
 template <int THREADS, int EPT, bool FUSED>
-__global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
+__global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
     constexpr int NSUB = CAP;  // sub-buckets per group
@@ -982,7 +1008,9 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     __shared__ uint32_t g_ch[MAXB];
     __shared__ uint32_t g_run[MAXB];
     __shared__ uint32_t g_seg[MAXB + 1];
-    __shared__ uint32_t sub_hist[NSUB + 1];
+    // sub-bucket counts, then their exclusive sums (16 bits: at most CAP)
+    __shared__ __align__(4) uint16_t sub_hist[NSUB + 2];
+    uint32_t *sub_w = reinterpret_cast<uint32_t *>(sub_hist);
     __shared__ uint32_t red[5 * (THREADS / 64) + 8];  // scans and statistics
     __shared__ uint32_t s_misc[8];
     // gather: tile map and the group's run in every tile; sort: (key bits,
@@ -991,6 +1019,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     // to the sub-bucket table, dead by then)
     constexpr int POOL = FUSED ? 8 * CAP : 12 * CAP;
     __shared__ __align__(16) unsigned char pool[POOL];
+    static_assert(CAP < 65536, "16-bit sub-bucket sums and candidate positions");
+    static_assert(2 * (NSUB + 2) >= 4 * (CAP / 2), "candidate list fits the sub-bucket table");
     static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= POOL,
                   "run tables must fit the sort pool");
     // run_pre: the group's records before each tile's run; run_base: the
@@ -1007,8 +1037,10 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
     constexpr bool fused = FUSED;
     const uint32_t rank0 = a.bucket_start[b0];
     const uint32_t tot = a.bucket_start[b1] - rank0;
-    if (tid == 0)
+    if (tid == 0) {
         s_misc[2] = 0;
+        s_misc[3] = 0;  // listed candidate pairs (fused LDS path)
+    }
 
     const int c_lo = a.bucket_cell[b0];
     const int n_gc = a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
@@ -1072,12 +1104,33 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             t_subbase[tid] = inc - ns;
         if (tid == 63)
             t_subbase[nb] = inc;
+        // pairs of every bucket, known before the sort: openers at even
+        // in-cell indices whose closer is in the same cell and in this
+        // group; pair k of the group opens at t_pa[b] + 2 (k - t_poff[b])
+        uint32_t cnt = 0;
+        if (tid < nb) {
+            const uint32_t lo = t_off[tid], hi = t_off[tid + 1];
+            const uint32_t cs = t_cs[tid];
+            const uint32_t fa = lo + ((rank0 + lo - cs) & 1u);
+            if (lo < hi) {
+                // openers f < lim: f < hi, f + 1 < tot, rank0 + f + 1 < cs + n_c
+                uint32_t lim = min(hi, tot - 1u);
+                lim = min(lim, cs + t_n[tid] - 1u - rank0);
+                cnt = fa < lim ? (lim - fa + 1u) >> 1 : 0u;
+            }
+            t_pa[tid] = fa;
+        }
+        const uint32_t pinc = wave_inclusive_scan(cnt);
+        if (tid < nb)
+            t_poff[tid] = pinc - cnt;
+        if (tid == 63)
+            t_poff[nb] = pinc;
     }
     const uint32_t cap_here =
         a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
     const bool lds_path = tot <= cap_here;
-    for (uint32_t i = tid; i <= (uint32_t)NSUB; i += THREADS)
-        sub_hist[i] = 0;
+    for (uint32_t i = tid; i < (uint32_t)(NSUB + 2) / 2; i += THREADS)
+        sub_w[i] = 0;
     __syncthreads();
 
     if (lds_path) {
@@ -1105,14 +1158,61 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
         // repeat the last record and are dropped below), so that the loads
         // of all EPT records are in flight together
         const uint32_t last = tot > 0 ? tot - 1 : 0;
+        const uint32_t step = step_of(a.step, a.step_dev);
+        // fused mode: phi of this thread's pairs (k = 2j, 2j + 1, j = tid +
+        // it THREADS), drawn while the records are in flight
+        constexpr int PITER = (CAP / 2 + 2 * THREADS - 1) / (2 * THREADS);
+        const uint32_t n_pairs = t_poff[nb];
+        const bool one_cell = n_gc == 1;  // openers every second position
+        double phi_pre[PITER][2];
         if (tot > 0 && fused) {
+            uint64_t rr[EPT];
+            int tt[EPT];
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const uint32_t li = min((uint32_t)(e * THREADS + tid), last);
-                const int t = tmap[li];
-                const uint32_t pos = run_base[t] + li;
-                const uint64_t r = a.rec_f[pos];
-                sid[e] = (uint32_t)(t_first + t) * (uint32_t)a.tile +
+                tt[e] = tmap[li];
+                rr[e] = a.rec_f[run_base[tt[e]] + li];
+            }
+#pragma unroll
+            for (int it = 0; it < PITER; ++it) {
+                const uint32_t j = (uint32_t)tid + (uint32_t)it * THREADS;
+                uint32_t qv[2] = {0, 0}, runv[2] = {0, 0};
+                bool valid[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const uint32_t k = 2 * j + (uint32_t)u;
+                    valid[u] = k < n_pairs;
+                    phi_pre[it][u] = 0.0;
+                    if (!valid[u])
+                        continue;
+                    int bl = 0;
+                    uint32_t f = t_pa[0] + 2u * k;
+                    if (!one_cell) {
+                        bl = upper_index(t_poff, nb, k);
+                        f = t_pa[bl] + 2u * (k - t_poff[bl]);
+                    }
+                    runv[u] = t_pc[bl].run;
+                    qv[u] = (rank0 + f - t_pc[bl].slot_base) >> 1;
+                }
+                if (valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1u &&
+                    runv[0] == runv[1]) {
+                    const WordPair wp = philox_words(a.seed, runv[0], step, SDM_STREAM_GAMMA,
+                                                     qv[0] >> 1);
+                    phi_pre[it][0] = word_to_uniform(wp.even);
+                    phi_pre[it][1] = word_to_uniform(wp.odd);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (valid[u])
+                            phi_pre[it][u] = word_to_uniform(
+                                philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u]));
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint64_t r = rr[e];
+                sid[e] = (uint32_t)(t_first + tt[e]) * (uint32_t)a.tile +
                          ((uint32_t)r & ((1u << RF_BKT_SHIFT) - 1u));
                 key[e] = (r >> RF_BKT_SHIFT) & ((1ull << (RF_XC_SHIFT - RF_BKT_SHIFT)) - 1ull);
                 cod[e] = (uint32_t)(r >> RF_XC_SHIFT);
@@ -1129,7 +1229,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 cod[e] = 0;
             }
         }
-        const uint32_t step = step_of(a.step, a.step_dev);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const uint32_t li = (uint32_t)(e * THREADS + tid);
@@ -1159,11 +1258,14 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
                 blk[e] = (uint8_t)bl;
                 sbk[e] = t_subbase[bl] + sub;
-                fp[e] = atomicAdd(&sub_hist[sbk[e]], 1u);  // rank among equal sub-buckets
+                // rank among equal sub-buckets: a 16-bit count in half of
+                // an LDS word (it never carries into the other half)
+                const uint32_t sh = (sbk[e] & 1u) * 16u;
+                fp[e] = (atomicAdd(&sub_w[sbk[e] >> 1], 1u << sh) >> sh) & 0xFFFFu;
             }
         }
         __syncthreads();
-        lds_exclusive_scan<THREADS, (NSUB + THREADS - 1) / THREADS>(sub_hist, (int)nsub, red);
+        lds_exclusive_scan16<THREADS, (NSUB + THREADS - 1) / THREADS>(sub_hist, (int)nsub, red);
         // rank by (key, s) inside the sub-bucket: the first RW entries of
         // every sub-bucket with independent (predicated) loads, the rare
         // longer ones in a loop.  Fused mode sorts (24 stored key bits, id)
@@ -1267,7 +1369,7 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
 
         // 3. ids and bound codes in sorted order, idx, seams
         uint32_t *RC = reinterpret_cast<uint32_t *>(pool);
-        uint32_t *RS = sub_hist;  // the sub-bucket table is dead after the ranks
+        uint32_t *RS = reinterpret_cast<uint32_t *>(pool + 4 * CAP);
         // position -> slot: the low two bits XORed with bits 4-5, so that
         // lanes reading positions 4 apart (two pairs per thread) hit
         // different LDS banks; a permutation within every 4 positions
@@ -1279,29 +1381,6 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             const uint32_t f = fp[e];
             RC[sw(f)] = cod[e];
             RS[sw(f)] = sid[e];
-        }
-        if (tid < 64) {
-            // pairs of every bucket: openers at even in-cell indices whose
-            // closer is in the same cell and in this group; pair k of the
-            // group opens at t_pa[b] + 2 (k - t_poff[b])
-            uint32_t cnt = 0;
-            if (tid < nb) {
-                const uint32_t lo = t_off[tid], hi = t_off[tid + 1];
-                const uint32_t cs = t_cs[tid];
-                const uint32_t fa = lo + ((rank0 + lo - cs) & 1u);
-                if (lo < hi) {
-                    // openers f < lim: f < hi, f + 1 < tot, rank0 + f + 1 < cs + n_c
-                    uint32_t lim = min(hi, tot - 1u);
-                    lim = min(lim, cs + t_n[tid] - 1u - rank0);
-                    cnt = fa < lim ? (lim - fa + 1u) >> 1 : 0u;
-                }
-                t_pa[tid] = fa;
-            }
-            const uint32_t inc = wave_inclusive_scan(cnt);
-            if (tid < nb)
-                t_poff[tid] = inc - cnt;
-            if (tid == 63)
-                t_poff[nb] = inc;
         }
         __syncthreads();
         for (uint32_t f = tid; f < tot; f += THREADS)
@@ -1320,10 +1399,8 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
                     continue;
                 SeamRec rec;
                 rec.s = RS[sw(f)];
-                rec.xi = a.xi[rec.s];
-                rec.v = a.attr[rec.s];
                 rec.rank = rank0 + f;
-                rec.cell = a.bucket_cell[b0 + bl];
+                rec.cell = c_lo + (int)t_cl[bl];
                 rec.cs = cs;
                 rec.n_c = t_n[bl];
                 rec.step = step;
@@ -1343,63 +1420,53 @@ __global__ __launch_bounds__(THREADS) void k_group(GroupArgs a)
             a.group_tot[g] = 0;
         }
 
-        // 4. pairs k = 2j, 2j + 1 per thread (adjacent pair slots share one
-        //    Philox block): the bound of eq. (3) from the codes against phi;
-        //    only pairs it does not rule out read xi and the volumes from the
-        //    state for the exact eq. (3), gamma and eqs. (4)-(6)
+        // 4. pairs k = 2j, 2j + 1 per thread (phi drawn during the gather):
+        //    the bound of eq. (3) from the codes against phi.
+        //    Pairs it does not rule out go to a list (position | bucket <<
+        //    16, in the dead sub-bucket table); after a barrier one thread
+        //    per listed pair reads xi and the attributes from the state
+        //    (one round trip for the group) for the exact eq. (3), gamma
+        //    and eqs. (4)-(6)
         Stats st{0, 0, 0, 0, 0};
-        const uint32_t n_pairs = t_poff[nb];
-        for (uint32_t j = tid; 2 * j < n_pairs; j += THREADS) {
-            uint32_t qv[2] = {0, 0}, runv[2] = {0, 0}, fv[2] = {0, 0};
-            int bv[2] = {0, 0};
-            double pub[2] = {0.0, 0.0};
-            bool valid[2];
+        uint32_t *CL = sub_w;  // the sub-bucket table is dead after the ranks
+#pragma unroll
+        for (int it = 0; it < PITER; ++it) {
+            const uint32_t j = (uint32_t)tid + (uint32_t)it * THREADS;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const uint32_t k = 2 * j + (uint32_t)u;
-                valid[u] = k < n_pairs;
-                if (!valid[u])
+                if (k >= n_pairs)
                     continue;
-                const int bl = upper_index(t_poff, nb, k);
-                const uint32_t f = t_pa[bl] + 2u * (k - t_poff[bl]);
+                int bl = 0;
+                uint32_t f = t_pa[0] + 2u * k;
+                if (!one_cell) {
+                    bl = upper_index(t_poff, nb, k);
+                    f = t_pa[bl] + 2u * (k - t_poff[bl]);
+                }
                 const PairCtx &pc = t_pc[bl];
-                bv[u] = bl;
-                fv[u] = f;
-                runv[u] = pc.run;
-                qv[u] = (rank0 + f - pc.slot_base) >> 1;
-                pub[u] = pair_bound(pc, RC[sw(f)], RC[sw(f + 1)]);
-            }
-            double phi[2] = {0.0, 0.0};
-            if (valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1u && runv[0] == runv[1]) {
-                const WordPair wp = philox_words(a.seed, runv[0], step, SDM_STREAM_GAMMA,
-                                                 qv[0] >> 1);
-                phi[0] = word_to_uniform(wp.even);
-                phi[1] = word_to_uniform(wp.odd);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-                    if (valid[u])
-                        phi[u] = word_to_uniform(
-                            philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u]));
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (!valid[u])
-                    continue;
-                const PairCtx &pc = t_pc[bv[u]];
-                if (pub[u] < phi[u]) {  // gamma = -0.0: no collision
+                const double pub = pair_bound(pc, RC[sw(f)], RC[sw(f + 1)]);
+                if (pub < phi_pre[it][u]) {  // gamma = -0.0: no collision
                     st.pairs += 1;
                     if (a.gamma_out)
-                        a.gamma_out[pc.gbase + qv[u]] = -0.0;
-                    continue;
+                        a.gamma_out[pc.gbase + ((rank0 + f - pc.slot_base) >> 1)] = -0.0;
+                } else {
+                    CL[atomicAdd(&s_misc[3], 1u)] = f | ((uint32_t)bl << 16);
                 }
-                const uint32_t f = fv[u];
-                const uint32_t sa = RS[sw(f)], sb2 = RS[sw(f + 1)];
-                const uint64_t xa = a.xi[sa], xb = a.xi[sb2];
-                const double va = a.attr[sa], vb = a.attr[sb2];
-                const double p = pair_prob(pc, xa, va, xb, vb);
-                finish_pair_v(a, pc, qv[u], p, phi[u], sa, xa, va, sb2, xb, vb, st);
             }
+        }
+        __syncthreads();
+        const uint32_t n_cand = s_misc[3];
+        for (uint32_t i = tid; i < n_cand; i += THREADS) {
+            const uint32_t f = CL[i] & 0xFFFFu;
+            const PairCtx &pc = t_pc[CL[i] >> 16];
+            const uint32_t q = (rank0 + f - pc.slot_base) >> 1;
+            const uint32_t sa = RS[sw(f)], sb2 = RS[sw(f + 1)];
+            const uint64_t xa = a.xi[sa], xb = a.xi[sb2];
+            const double va = a.attr[sa], vb = a.attr[sb2];
+            const double phi =
+                word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
+            const double p = pair_prob(pc, xa, va, xb, vb);
+            finish_pair_v(a, pc, q, p, phi, sa, xa, va, sb2, xb, vb, st);
         }
         if (a.counters)
             store_group_stats<THREADS>(a, g, st, red);
@@ -1507,10 +1574,12 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
                 const uint32_t step = op.step;
                 const PairCtx pc = pair_ctx(a, op.cell, op.cs, op.n_c);
                 const uint32_t q = (op.rank - pc.slot_base) >> 1;
-                const double p = pair_prob(pc, op.xi, op.v, cl.xi, cl.v);
+                const uint64_t xo = a.xi[op.s], xc = a.xi[cl.s];
+                const double vo = a.attr[op.s], vc = a.attr[cl.s];
+                const double p = pair_prob(pc, xo, vo, xc, vc);
                 const double phi =
                     word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
-                finish_pair_v(a, pc, q, p, phi, op.s, op.xi, op.v, cl.s, cl.xi, cl.v, st);
+                finish_pair_v(a, pc, q, p, phi, op.s, xo, vo, cl.s, xc, vc, st);
             }
         }
     }

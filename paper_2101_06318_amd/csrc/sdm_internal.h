@@ -77,10 +77,9 @@ constexpr int RF_XC_SHIFT = 43;   // bits 19-42: 24 key bits; bits 43-50: xi bou
 constexpr int RF_VC_SHIFT = 51;   // bits 51-63: volume bound code
 
 // Pair that straddles two groups: the opener's record, written by the
-// group holding it and completed by the finish kernel.
+// group holding it and completed by the finish kernel (which reads the two
+// SDs' multiplicities and volumes from the state).
 struct SeamRec {
-    uint64_t xi;
-    double v;
     uint32_t s;
     uint32_t rank;
     int32_t cell;
