@@ -200,6 +200,19 @@ __device__ __forceinline__ int upper_index(const uint32_t *tab, int n, uint32_t 
     return lo;
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup i to XCD
+// i mod 8), each with its own L2.  Group g's runs end in the cache lines
+// where group g + 1's begin, so consecutive groups go to the same XCD: XCD x
+// takes the x-th of eight contiguous ranges of groups, in order.  A
+// bijection of [0, n).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_local_index(int b, int n)
+{
+    const int x = b % N_XCD, i = b / N_XCD;
+    const int per = n / N_XCD, rem = n % N_XCD;
+    return x * per + min(x, rem) + i;
+}
+
 // Inclusive scan over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
 {
@@ -1029,7 +1042,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     uint32_t *run_base = reinterpret_cast<uint32_t *>(pool + 2 * CAP + 4 * (MAX_TILES + 1));
 
     const int tid = threadIdx.x;
-    const int g = blockIdx.x;
+    const int g = xcd_local_index((int)blockIdx.x, (int)gridDim.x);
     const int b0 = a.group_first[g], b1 = a.group_first[g + 1];
     const int nb = b1 - b0;
     const int nt = a.n_tiles;
