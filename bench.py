@@ -15,15 +15,18 @@ Workloads (--workload, default box):
   ensemble   1024 independent boxes of 2^8..2^16 SDs (log-uniform), Golovin
              and gravitational kernels alternating, advanced together
              (sdm_batch_step) with the autotuned schedule.
-  golovin    the paper's validation run itself: the box with 2^13 SDs (seed 1)
-             for 3600 steps from its initial state, timed as graph replays of
-             1200 steps; moments at 1200, 2400 and 3600 s against the Golovin
-             closed form (eq. 7 moments).
+  golovin    the paper's validation run itself: the box with 2^13 SDs for
+             3600 steps from its initial state, 16 seeds, each timed as graph
+             replays of 1200 steps; mean moments at 1200, 2400 and 3600 s
+             against the Golovin closed form (eq. 7 moments).
   surrogate  the moment surrogate's step for the 16384 cells of the grid
              (features, hull test, bf16 MFMA forward, moment update), beside
              one SDM step of the same grid (cell-steps/s of both).
   train      the surrogate's training step: a minibatch of 4096 samples
              through forward, MSE gradient, backward and Adam (samples/s).
+
+With the box workload (the default) the line also carries `sub_results`:
+every other workload measured in the same run, without oracle baselines.
 
 W warm-up steps run first.  Then K steps are captured in one HIP graph,
 replayed once untimed and five times timed, each bracketed by
@@ -32,8 +35,9 @@ the eager pass below instead).
 A separate eager pass of K steps on one stream, where the library records
 HIP events between its kernels, gives the per-kernel durations for the
 roofline of the dominant kernel (eager_ms_per_step is that pass's wall
-time).  The oracle (plain C, one host thread) is timed on a bounded sample
-of the same workload (cpu_baseline).
+time).  The oracle (plain C, one host thread pinned to one core) is timed
+on a bounded sample of the same workload (cpu_baseline); the ensemble also
+reports one oracle process per host core (cpu_baseline_whole_host).
 """
 from __future__ import annotations
 
@@ -61,16 +65,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_record(kernel, workload):
-    """Counter-measured bytes per launch, if profiles/ holds a record taken
-    on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+def traffic_record(workload):
+    """Counter-measured HBM bytes of one whole step (every kernel of the
+    step: FETCH_SIZE and WRITE_SIZE, each scaled by what the counters read for
+    a plain copy of known size), if profiles/ holds a record taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_step_%s.json" % workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_step")
 
 
 class HipEvent:
@@ -124,22 +130,39 @@ TIMING = ("K steps captured in one HIP graph, median of 5 timed replays (value, 
 TIMING_EAGER = "K eager steps on one stream, HIP events between the kernels"
 
 
-def algorithmic_bytes(pairs, f_coll, per_pair_read, per_pair_write_idx, per_pair_coll):
-    """Algorithmic HBM bytes of one step, split per kernel: per pair, the
-    state of two SDs read and the Index read (charged to the tile kernel),
-    the Index written and the write-back of a colliding pair (charged to
-    the group kernel, times the collision fraction)."""
-    return {"step": pairs * (per_pair_read + per_pair_write_idx + per_pair_coll * f_coll),
-            "k_tile+k_scan": pairs * per_pair_read,
-            "k_group": pairs * (per_pair_write_idx + per_pair_coll * f_coll),
-            "k_finish": 0.0}
+def algorithmic_bytes(pairs, f_coll, per_pair, per_pair_coll):
+    """Algorithmic HBM bytes of one step: per pair, the state of two SDs
+    read, their Index entries written and read back, and the write-back of
+    a colliding pair times the collision fraction."""
+    return pairs * (per_pair + per_pair_coll * f_coll)
+
+
+def event_overhead_ms(torch, lib, stream, n=50):
+    """Mean HIP-event interval around an empty kernel (torch's zero-cycle
+    spin) on the stream: the dispatch and event cost that every marked
+    interval carries besides its kernel's own duration."""
+    ev = [(HipEvent(lib), HipEvent(lib)) for _ in range(n)]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for a, b in ev:
+            a.record(stream)
+            torch.cuda._sleep(0)
+            b.record(stream)
+    torch.cuda.synchronize()
+    vals = sorted(a.elapsed_ms(b) for a, b in ev)
+    for a, b in ev:
+        a.destroy()
+        b.destroy()
+    return vals[len(vals) // 2]
 
 
 def timed_steps(sdm, torch, run_step, K, lib):
     """K steps on one stream with the library's event marks; returns the total
-    wall time (ms) and the mean duration of each marked interval."""
+    wall time (ms) and the mean duration of each marked interval, less the
+    event interval around an empty kernel (the per-interval overhead)."""
     ev = [[HipEvent(lib) for _ in range(4)] for _ in range(K)]
     stream = torch.cuda.Stream()
+    over = event_overhead_ms(torch, lib, stream)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -157,7 +180,9 @@ def timed_steps(sdm, torch, run_step, K, lib):
     for row in ev:
         for e in row:
             e.destroy()
-    return total_ms, {k: sum(v) / len(v) for k, v in per.items()}, stream
+    kms = {k: max(sum(v) / len(v) - over, 0.0) for k, v in per.items()}
+    kms["event_overhead_subtracted"] = over
+    return total_ms, kms, stream
 
 
 def graph_ms(torch, run_step, K, stream):
@@ -187,12 +212,35 @@ def graph_ms(torch, run_step, K, stream):
         return None
 
 
-def roofline(ab, kernel_ms, workload):
-    dom = max(kernel_ms, key=kernel_ms.get)
-    achieved = ab[dom] / (kernel_ms[dom] / 1e3) / 1e9
+def roofline(b_alg, kernel_ms, workload):
+    """The dominant (longest) kernel against the step's algorithmic bytes,
+    which one launch of it covers (it processes every pair of the step):
+    achieved = B_alg / its mean duration.  traffic: counter bytes of the
+    whole step, when measured on the current sources."""
+    dom = max((k for k in kernel_ms if k in INTERVALS), key=kernel_ms.get)
+    achieved = b_alg / (kernel_ms[dom] / 1e3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_record(dom, workload)}
+            "traffic": traffic_record(workload), "algorithmic_bytes": b_alg}
+
+
+def step_roofline(b_alg, step_ms):
+    gbs = b_alg / (step_ms / 1e3) / 1e9
+    return {"bound": "hbm", "bytes_per_step": b_alg, "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+
+def host_oracle(fn, seconds):
+    """Runs fn(deadline) (the oracle on a bounded sample) pinned to one host
+    core; returns (its result, the core, host description)."""
+    from oracle.hostbench import host_info
+    cpus = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {cpus[0]})
+    try:
+        res = fn(time.perf_counter() + seconds)
+    finally:
+        os.sched_setaffinity(0, set(cpus))
+    return res, cpus[0], host_info()
 
 
 def base_line(metric, value, unit, K, W, ms, dtype, config):
@@ -202,6 +250,28 @@ def base_line(metric, value, unit, K, W, ms, dtype, config):
 
 
 # ---------------------------------------------------------------- workloads
+def oracle_box_sample(np, w, seed, deadline, cell_id_fn=None, n_cell=1):
+    """Whole oracle steps from the initial state until the deadline."""
+    import oracle
+    n = w["xi"].shape[0]
+    s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
+    t0 = time.perf_counter()
+    npairs = steps = 0
+    while steps == 0 or time.perf_counter() < deadline:
+        cid = cell_id_fn(steps) if cell_id_fn else None
+        s = oracle.step(s["xi"], s["attr"], cid, n_cell, w["dv"], s["idx"], s["n_live"],
+                        dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
+                        seed=seed, run=0, step=steps)
+        npairs += int(s["counters"][oracle.CNT_PAIRS])
+        steps += 1
+    return npairs, steps, time.perf_counter() - t0
+
+
+def cpu_line(value, unit, seconds, core, host, sample):
+    return {"value": value, "unit": unit, "cores": 1, "kind": "oracle",
+            "seconds": round(seconds, 3), "pinned_core": core, "host": host, "sample": sample}
+
+
 def bench_box(args, sdm, torch, np, workloads):
     n_sd = 1 << args.log2_n_sd
     w = workloads.box(n_sd, seed=2)
@@ -226,10 +296,10 @@ def bench_box(args, sdm, torch, np, workloads):
     pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) // K
     f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
     assert ctx.read_errors() == 0
-    # per pair: xi and v of two SDs (32 B) and their Index entries (8 B)
-    # read, Index written (8 B), xi and v of both written back on a
-    # collision (32 B): 48 + 32 f_coll
-    ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
+    # per pair: xi and v of two SDs (32 B) read, their Index entries written
+    # and read back (16 B); xi and v of both written back on a collision
+    # (32 B): 48 + 32 f_coll
+    b_alg = algorithmic_bytes(pairs, f_coll, 48.0, 32.0)
     workload = "golovin_box_2_%d" % args.log2_n_sd
     step_ms = gms if gms else total_ms / K
     out = base_line("SDM pair-steps/s at n_sd=2^%d" % args.log2_n_sd,
@@ -239,35 +309,21 @@ def bench_box(args, sdm, torch, np, workloads):
                      "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 2,
                      "timing": TIMING if gms else TIMING_EAGER,
                      "n_live": int(st.n_live.item()), "collision_fraction": f_coll})
-    out["roofline"] = roofline(ab, kms, workload)
+    out["roofline"] = roofline(b_alg, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
     out["eager_ms_per_step"] = total_ms / K
-    step_gbs = ab["step"] / (step_ms / 1e3) / 1e9
-    out["step_roofline"] = {"bound": "hbm", "bytes_per_step": ab["step"], "achieved": step_gbs,
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": step_gbs / HBM_PEAK_GBS}
+    out["step_roofline"] = step_roofline(b_alg, step_ms)
     out["cpu_baseline"] = None
-    if not args.no_cpu_baseline:
-        import oracle
-        n = n_sd
-        s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
-        t0 = time.perf_counter()
-        npairs = steps = 0
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            s = oracle.step(s["xi"], s["attr"], None, 1, w["dv"], s["idx"], s["n_live"],
-                            dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
-                            seed=2, run=0, step=steps)
-            npairs += int(s["counters"][oracle.CNT_PAIRS])
-            steps += 1
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
-            "kind": "oracle", "seconds": round(dt, 3),
-            "sample": "the first %d steps of the 2^%d-SD Golovin box (seed 2) from its initial "
-                      "state, oracle (plain C, one thread, qsort-based shuffle)"
-                      % (steps, args.log2_n_sd)}
     ctx.close()
+    if not args.no_cpu_baseline:
+        (npairs, steps, dt), core, host = host_oracle(
+            lambda dl: oracle_box_sample(np, w, 2, dl), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_line(
+            npairs / dt, "pair-steps/s", dt, core, host,
+            "the first %d steps of the 2^%d-SD Golovin box (seed 2) from its initial state, "
+            "oracle (plain C, one thread pinned to one core, qsort-based shuffle)"
+            % (steps, args.log2_n_sd))
     return out
 
 
@@ -280,7 +336,6 @@ def bench_grid(args, sdm, torch, np, workloads):
     k = sdm.kernel(w["kernel_id"], w["kparams"])
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     r = sdm.rng(3, 0, 0, step_dev=step_dev)
-    reass_ms = []
 
     def run_step(t, stream, ev):
         ctx.reassign(st.cell_id, n_sd, n_cell, r, stream=stream)
@@ -298,10 +353,10 @@ def bench_grid(args, sdm, torch, np, workloads):
     pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
     f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
     assert ctx.read_errors() == 0
-    # per pair: xi, two attributes and the cell id of two SDs (56 B) and
-    # their Index entries (8 B) read, Index written (8 B), xi and both
+    # per pair: xi, two attributes and the cell id of two SDs (56 B) read,
+    # their Index entries written and read back (16 B); xi and both
     # attributes of two SDs written back on a collision (48 B): 72 + 48 f_coll
-    ab = algorithmic_bytes(pairs, f_coll, 64.0, 8.0, 48.0)
+    b_alg = algorithmic_bytes(pairs, f_coll, 72.0, 48.0)
     workload = "grid_128x128"
     step_ms = gms if gms else total_ms / K
     out = base_line("SDM pair-steps/s on the 128x128 grid", pairs / (step_ms / 1e3),
@@ -309,32 +364,44 @@ def bench_grid(args, sdm, torch, np, workloads):
                     {"workload": workload, "n_sd": n_sd, "cells": n_cell, "kernel": "geometric",
                      "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 3,
                      "reassignment": "every step, inside the timed region",
-                     "pairs_per_step": pairs, "collision_fraction": f_coll, "timing": TIMING if gms else TIMING_EAGER})
+                     "pairs_per_step": pairs, "collision_fraction": f_coll,
+                     "timing": TIMING if gms else TIMING_EAGER})
     out["cell_steps_per_s"] = n_cell / (step_ms / 1e3)
-    out["roofline"] = roofline(ab, kms, workload)
+    out["roofline"] = roofline(b_alg, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
     out["eager_ms_per_step"] = total_ms / K
+    out["step_roofline"] = step_roofline(b_alg, step_ms)
     out["cpu_baseline"] = None
+    ctx.close()
     if not args.no_cpu_baseline:
         import oracle
-        s = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
-        t0 = time.perf_counter()
-        npairs = steps = 0
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            cid = oracle.reassign(n_sd, n_cell, 3, steps)
-            s = oracle.step(s["xi"], s["attr"], cid, n_cell, w["dv"], s["idx"], s["n_live"],
-                            dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"], seed=3,
-                            run=0, step=steps)
-            npairs += int(s["counters"][oracle.CNT_PAIRS])
-            steps += 1
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
-                               "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "%d reassignment + step passes of the full grid, "
-                                         "oracle (plain C, one thread)" % steps}
-    ctx.close()
+        (npairs, steps, dt), core, host = host_oracle(
+            lambda dl: oracle_box_sample(np, w, 3, dl,
+                                         lambda t: oracle.reassign(n_sd, n_cell, 3, t),
+                                         n_cell), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_line(npairs / dt, "pair-steps/s", dt, core, host,
+                                       "%d reassignment + step passes of the full grid, "
+                                       "oracle (plain C, one thread pinned to one core)" % steps)
     return out
+
+
+def whole_host_ensemble(seconds):
+    """One oracle process per usable host core (at most 16), each on its
+    share of the 1024 runs; their pairs summed over the common wall time."""
+    import subprocess
+    P = min(16, len(os.sched_getaffinity(0)))
+    procs = [subprocess.Popen([sys.executable, "-m", "oracle.hostbench", "--core", str(c),
+                               "--of", str(P), "--seconds", str(seconds)],
+                              cwd=ROOT, stdout=subprocess.PIPE, text=True) for c in range(P)]
+    res = []
+    for p in procs:
+        o, _ = p.communicate(timeout=seconds + 300)
+        if p.returncode != 0:
+            raise RuntimeError("oracle host process failed")
+        res.append(json.loads(o.strip().splitlines()[-1]))
+    wall = max(r["seconds"] for r in res)
+    return sum(r["pairs"] for r in res) / wall, P, wall
 
 
 def bench_ensemble(args, sdm, torch, np, workloads):
@@ -352,54 +419,76 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     def run_step(t, stream, ev):
         b.step(st, ens["dt"], r, stream=stream, events=ev, step_advance=step_dev)
 
-    for t in range(args.warmup):
-        run_step(t, None, None)
-    torch.cuda.synchronize()
-    c0 = st.counters.cpu().numpy().copy()
+    def measure():
+        for t in range(args.warmup):
+            run_step(t, None, None)
+        torch.cuda.synchronize()
+        c0 = st.counters.cpu().numpy().copy()
+        total_ms, kms, stream = timed_steps(sdm, torch, run_step, args.steps, sdm.lib())
+        c1 = st.counters.cpu().numpy()
+        gms = None if args.eager else graph_ms(torch, run_step, args.steps, stream)
+        return total_ms, kms, gms, c0, c1
+
+    # the schedule the library uses without tuning (0), then the tuned one
+    b.set_schedule(0)
+    d_total, d_kms, d_gms, _, _ = measure()
+    b.set_schedule(chosen)
+    total_ms, kms, gms, c0, c1 = measure()
     K = args.steps
-    total_ms, kms, stream = timed_steps(sdm, torch, run_step, K, sdm.lib())
-    c1 = st.counters.cpu().numpy()
-    gms = None if args.eager else graph_ms(torch, run_step, K, stream)
     pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
     f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
     assert ctx.read_errors() == 0
-    ab = algorithmic_bytes(pairs, f_coll, 40.0, 8.0, 32.0)
+    b_alg = algorithmic_bytes(pairs, f_coll, 48.0, 32.0)
     workload = "ensemble_1024"
     step_ms = gms if gms else total_ms / K
+    d_step_ms = d_gms if d_gms else d_total / K
     out = base_line("SDM pair-steps/s, 1024-run batched ensemble", pairs / (step_ms / 1e3),
                     "pair-steps/s", K, args.warmup, step_ms, "f64",
                     {"workload": workload, "runs": len(segs), "n_sd": int(sum(s[1] for s in segs)),
                      "kernels": "golovin (even runs), geometric (odd runs)", "dt_s": ens["dt"],
                      "seed": 4, "schedule": chosen, "pairs_per_step": pairs,
                      "collision_fraction": f_coll, "timing": TIMING if gms else TIMING_EAGER})
-    out["roofline"] = roofline(ab, kms, workload)
+    out["default_schedule"] = {"schedule": 0, "ms_per_step": d_step_ms,
+                               "value": pairs / (d_step_ms / 1e3), "kernel_ms": d_kms}
+    out["roofline"] = roofline(b_alg, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
     out["eager_ms_per_step"] = total_ms / K
+    out["step_roofline"] = step_roofline(b_alg, step_ms)
     out["cpu_baseline"] = None
+    b.close()
+    ctx.close()
     if not args.no_cpu_baseline:
         import oracle
         runs = ens["runs"]
-        states = [dict(xi=m["xi"], attr=m["attr"], idx=np.arange(m["n_sd"], dtype=np.uint32),
-                       n_live=m["n_sd"]) for m in runs]
-        t0 = time.perf_counter()
-        npairs = done = 0
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            r_ = done % len(runs)
-            m, s = runs[r_], states[r_]
-            s = oracle.step(s["xi"], s["attr"], None, 1, [m["dv"]], s["idx"], s["n_live"],
-                            dt=ens["dt"], kernel_id=m["kernel_id"], kparams=m["kparams"],
-                            seed=4, run=m["run"], step=done // len(runs))
-            states[r_] = s
-            npairs += int(s["counters"][oracle.CNT_PAIRS])
-            done += 1
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s", "cores": 1,
-                               "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "%d run-steps (the 1024 runs in turn, each from its "
-                                         "initial state), oracle (plain C, one thread)" % done}
-    b.close()
-    ctx.close()
+
+        def sample(deadline):
+            states = [dict(xi=m["xi"], attr=m["attr"], idx=np.arange(m["n_sd"], dtype=np.uint32),
+                           n_live=m["n_sd"]) for m in runs]
+            t0 = time.perf_counter()
+            npairs = done = 0
+            while done == 0 or time.perf_counter() < deadline:
+                r_ = done % len(runs)
+                m, s = runs[r_], states[r_]
+                s = oracle.step(s["xi"], s["attr"], None, 1, [m["dv"]], s["idx"], s["n_live"],
+                                dt=ens["dt"], kernel_id=m["kernel_id"], kparams=m["kparams"],
+                                seed=4, run=m["run"], step=done // len(runs))
+                states[r_] = s
+                npairs += int(s["counters"][oracle.CNT_PAIRS])
+                done += 1
+            return npairs, done, time.perf_counter() - t0
+
+        (npairs, done, dt), core, host = host_oracle(sample, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_line(npairs / dt, "pair-steps/s", dt, core, host,
+                                       "%d run-steps (the 1024 runs in turn, each from its "
+                                       "initial state), oracle (plain C, one thread pinned to "
+                                       "one core)" % done)
+        v, P, wall = whole_host_ensemble(args.cpu_seconds)
+        out["cpu_baseline_whole_host"] = {
+            "value": v, "unit": "pair-steps/s", "cores": P, "kind": "oracle",
+            "seconds": round(wall, 3),
+            "sample": "%d oracle processes, one per host core, each on every %d-th run of the "
+                      "1024 in turn from the initial states" % (P, P)}
     return out
 
 
@@ -412,14 +501,17 @@ def golovin_moments(t, N0, b, vbar):
     return N0 * (1.0 - tau), N0 * vbar, 2.0 * N0 * vbar ** 2 / (1.0 - tau) ** 2
 
 
-def bench_golovin(args, sdm, torch, np, workloads):
+def golovin_run(sdm, torch, np, workloads, seed):
+    """One 2^13-SD box (initial state and Philox seed `seed`) over 3600 s as
+    three graph replays of 1200 steps; moments at 1200, 2400, 3600 s and the
+    replay time."""
     n_sd = 1 << 13
-    w = workloads.box(n_sd, seed=1)
+    w = workloads.box(n_sd, seed=seed)
     ctx = sdm.Context(n_sd, 1, 1)
     st = sdm.State(w["xi"], w["attr"], None, 1)
     k = sdm.kernel(w["kernel_id"], w["kparams"])
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
-    r = sdm.rng(1, 0, 0, step_dev=step_dev)
+    r = sdm.rng(seed, 0, 0, step_dev=step_dev)
     kw = dict(dv=w["dv"][0], step_advance=step_dev)
     ctx.prepare_step(st, w["dt"], k, r, **kw)
     stream = torch.cuda.Stream()
@@ -438,9 +530,9 @@ def bench_golovin(args, sdm, torch, np, workloads):
     st.counters.zero_()
     step_dev.zero_()
     M = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
-    out_m = []
+    moms = []
     total_ms = 0.0
-    for t_end in (1200, 2400, 3600):
+    for _ in range(3):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -452,40 +544,68 @@ def bench_golovin(args, sdm, torch, np, workloads):
         total_ms += e0.elapsed_time(e1)
         ctx.moments(M, st.xi, st.attr[0], st.idx, st.cell_start, 1, dv=w["dv"][0])
         torch.cuda.synchronize()
-        m = M.cpu().numpy()[0]
-        ref = golovin_moments(float(t_end), w["N0"], w["b"], w["vbar"])
-        out_m.append({"t_s": t_end, "M0_rel_err": float(m[0] / ref[0] - 1.0),
-                      "M1_rel_err": float(m[1] / ref[1] - 1.0),
-                      "M2_rel_err": float(m[2] / ref[2] - 1.0)})
+        moms.append(M.cpu().numpy()[0].copy())
     del g
-    K = 3 * seg
-    assert int(step_dev.item()) == K and ctx.read_errors() == 0
+    assert int(step_dev.item()) == 3 * seg and ctx.read_errors() == 0
+    ctx.close()
+    return w, np.array(moms), total_ms
+
+
+def bench_golovin(args, sdm, torch, np, workloads):
+    """The paper's validation run (Sec. 4): the Golovin box with 2^13 SDs over
+    3600 s, 16 seeds; mean moments against the closed form of eq. (7).
+    Timing is seed 1's three graph replays."""
+    seeds = list(range(1, 17))
+    runs = [golovin_run(sdm, torch, np, workloads, s) for s in seeds]
+    w, _, total_ms = runs[0]
+    n_sd = 1 << 13
+    K = 3600
+    M = np.stack([m for _, m, _ in runs])  # [seed][time][k]
+    out_m = []
+    ok = True
+    for it, t_end in enumerate((1200, 2400, 3600)):
+        ref = golovin_moments(float(t_end), w["N0"], w["b"], w["vbar"])
+        row = {"t_s": t_end}
+        for kk, name in ((0, "M0"), (1, "M1"), (2, "M2")):
+            vals = M[:, it, kk] / ref[kk]
+            mean = float(vals.mean())
+            se = float(vals.std(ddof=1) / np.sqrt(len(seeds)))
+            row[name + "_mean_rel_err"] = mean - 1.0
+            row[name + "_std_err"] = se
+            if kk != 1:
+                ok = ok and abs(mean - 1.0) <= 3.0 * se + 0.01
+        out_m.append(row)
     out = base_line("SDM pair-steps/s, 2^13-SD Golovin box over 3600 s",
                     (n_sd // 2) * K / (total_ms / 1e3), "pair-steps/s", K, 0, total_ms / K,
                     "f64", {"workload": "golovin_box_2_13_3600s", "n_sd": n_sd, "cells": 1,
-                            "kernel": "golovin", "b_per_s": w["b"], "dt_s": w["dt"], "seed": 1,
+                            "kernel": "golovin", "b_per_s": w["b"], "dt_s": w["dt"],
+                            "seeds": "1-16 (timing: seed 1)",
                             "timing": "three graph replays of 1200 steps"})
     out["wall_s_3600_steps"] = total_ms / 1e3
-    out["golovin_moments"] = out_m
+    out["golovin_moments_16_seeds"] = out_m
+    out["golovin_within_tolerance"] = ok
+    out["golovin_tolerance"] = "|mean/closed form - 1| <= 3 standard errors + 1 % for M0 and M2"
     out["roofline"] = None
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
-        import oracle
-        s_ = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32), n_live=n_sd)
-        t0 = time.perf_counter()
-        npairs = steps = 0
-        while time.perf_counter() - t0 < args.cpu_seconds and steps < 3600:
-            s_ = oracle.step(s_["xi"], s_["attr"], None, 1, w["dv"], s_["idx"], s_["n_live"],
-                             dt=w["dt"], kernel_id=w["kernel_id"], kparams=w["kparams"],
-                             seed=1, run=0, step=steps)
-            npairs += int(s_["counters"][oracle.CNT_PAIRS])
-            steps += 1
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": npairs / dt, "unit": "pair-steps/s",
-                               "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "the first %d of the 3600 steps, oracle (plain C, one "
-                                         "thread)" % steps}
-    ctx.close()
+        def sample(deadline):
+            import oracle
+            s_ = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n_sd, dtype=np.uint32),
+                      n_live=n_sd)
+            t0 = time.perf_counter()
+            npairs = steps = 0
+            while (steps == 0 or time.perf_counter() < deadline) and steps < 3600:
+                s_ = oracle.step(s_["xi"], s_["attr"], None, 1, w["dv"], s_["idx"],
+                                 s_["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
+                                 kparams=w["kparams"], seed=1, run=0, step=steps)
+                npairs += int(s_["counters"][oracle.CNT_PAIRS])
+                steps += 1
+            return npairs, steps, time.perf_counter() - t0
+
+        (npairs, steps, dt), core, host = host_oracle(sample, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_line(npairs / dt, "pair-steps/s", dt, core, host,
+                                       "the first %d of the 3600 steps of seed 1, oracle "
+                                       "(plain C, one thread pinned to one core)" % steps)
     return out
 
 
@@ -707,6 +827,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="skip the graph-replay measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-sub", action="store_true",
+                    help="box workload: skip the other workloads' sub-results")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the SDM step runs and is measured on one MI355X only (no sharded "
@@ -736,7 +858,39 @@ def main():
           "golovin": bench_golovin, "surrogate": bench_surrogate,
           "train": bench_train}[args.workload]
     out = fn(args, sdm, torch, np, workloads)
+    if args.workload == "box" and not args.no_sub:
+        out["sub_results"] = sub_results(args, sdm, torch, np, workloads)
     print(json.dumps(out), flush=True)
+
+
+SUB_KEYS = ("metric", "value", "unit", "ms_per_step", "dtype", "config", "kernel_ms",
+            "roofline", "step_roofline", "cell_steps_per_s", "sdm_cell_steps_per_s",
+            "speedup_vs_sdm", "default_schedule", "golovin_moments_16_seeds",
+            "golovin_within_tolerance", "golovin_tolerance", "wall_s_3600_steps",
+            "surrogate_gate")
+
+
+def sub_results(args, sdm, torch, np, workloads):
+    """The other workloads, measured in the same run (no oracle baselines:
+    `--workload X` gives each its own line with one)."""
+    import copy
+    res = {}
+    for name, fn in (("grid", bench_grid), ("ensemble", bench_ensemble),
+                     ("golovin", bench_golovin), ("surrogate", bench_surrogate),
+                     ("train", bench_train)):
+        a = copy.copy(args)
+        a.no_cpu_baseline = True
+        a.steps = min(args.steps, 100)
+        t0 = time.perf_counter()
+        try:
+            o = fn(a, sdm, torch, np, workloads)
+            res[name] = {k: o[k] for k in SUB_KEYS if k in o}
+        except Exception as e:  # reported in the line, the headline stands
+            res[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+        res[name]["wall_s"] = round(time.perf_counter() - t0, 2)
+        print("bench: sub-result %s done (%.1f s)" % (name, res[name]["wall_s"]),
+              file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":
