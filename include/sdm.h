@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SDM_ABI_VERSION 1
+#define SDM_ABI_VERSION 2
 
 typedef enum {
     SDM_OK = 0,
@@ -69,9 +69,25 @@ enum { SDM_STREAM_SHUFFLE = 0, SDM_STREAM_GAMMA = 1, SDM_STREAM_INIT = 2,
  *                 otherwise [m/s]: each law up to where it meets the next
  *  CONSTANT       p[0]
  *  MULTIPLICATIVE p[0] v1 v2
- * (Golovin, constant and multiplicative: Sec. 2.1; gravitational: Sec. 4.) */
+ *  TABULATED      p[0] T[min(i1, i2)][max(i1, i2)]: any kernel, tabulated
+ *                 by the caller on a binary-logarithmic grid of volumes.
+ *                 i(v) = code(v) - lo clamped to [0, n - 1], where code(v)
+ *                 is the IEEE-754 bit pattern of v read as an unsigned
+ *                 integer and shifted right by 52 - m (2^m cells per
+ *                 octave: cell code c holds the volumes whose pattern
+ *                 starts with c); lo = p[1], n = p[2], m = p[3] (integers
+ *                 held in doubles; 1 <= n <= 4096, 0 <= m <= 12).  T is
+ *                 table[n * n], row-major, read only on or above the
+ *                 diagonal, so the kernel is symmetric.  Only integer
+ *                 operations pick the cell, so every backend gives the same
+ *                 bits.  The fused step rules out no pair by a bound for
+ *                 this kernel: every pair reads its SDs.
+ * (Golovin, constant and multiplicative: Sec. 2.1; gravitational: Sec. 4;
+ * the tabulated form is the plug-in point for the general kernels Sec. 5
+ * names as an extension.) */
 enum { SDM_KERNEL_GOLOVIN = 0, SDM_KERNEL_GEOMETRIC = 1,
-       SDM_KERNEL_CONSTANT = 2, SDM_KERNEL_MULTIPLICATIVE = 3 };
+       SDM_KERNEL_CONSTANT = 2, SDM_KERNEL_MULTIPLICATIVE = 3,
+       SDM_KERNEL_TABULATED = 4 };
 
 /* Counter slots (uint64_t counters_dev[8]). */
 enum { SDM_CNT_PAIRS = 0,      /* flagged pairs visited                      */
@@ -89,6 +105,9 @@ typedef struct {
     int32_t id;              /* SDM_KERNEL_*                                 */
     int32_t reserved;
     double  p[4];            /* kernel parameters (see above)                */
+    const double *table;     /* SDM_KERNEL_TABULATED: device double[n * n],  */
+                             /* caller-owned, read while the calls (or a     */
+                             /* graph that captured them) run; else NULL     */
 } sdm_kernel;
 
 typedef struct {

@@ -27,7 +27,7 @@ _lock = threading.Lock()
 _lib = None
 
 STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP = range(5)
-KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE = range(4)
+KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE, KERNEL_TABULATED = range(5)
 CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2 = range(5)
 N_COUNTERS = 8
 
@@ -59,7 +59,7 @@ def lib():
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("kernel_id", C.c_int32),
                 ("kparams", C.c_double * 4), ("seed", C.c_uint64),
-                ("run", C.c_uint32), ("step", C.c_uint32)]
+                ("run", C.c_uint32), ("step", C.c_uint32), ("table", C.c_void_p)]
 
 
 _P = C.c_void_p
@@ -80,8 +80,8 @@ def _declare(L):
         "sdmo_cell_sort": (C.c_int, [_P, _P, _I64, _P, _I32]),
         "sdmo_shuffle_per_cell": (C.c_int, [_P, _P, _I64, _P, _I32, _P]),
         "sdmo_flag_pairs": (None, [_P, _P, _P, _P, _I64]),
-        "sdmo_kernel_value": (_D, [_I32, _P, _D, _D]),
-        "sdmo_coalescence_kernel": (None, [_P, _P, _P, _P, _I64, _I32, _P]),
+        "sdmo_kernel_value": (_D, [_I32, _P, _P, _D, _D]),
+        "sdmo_coalescence_kernel": (None, [_P, _P, _P, _P, _I64, _I32, _P, _P]),
         "sdmo_times_max": (None, [_P, _P, _P, _P, _I64]),
         "sdmo_pair_scale": (_U64, [_U64]),
         "sdmo_normalize": (None, [_P, _D, _P, _P, _P, _P, _P, _I64]),
@@ -178,18 +178,24 @@ def flag_pairs(cell_id, cell_start, idx, n_live):
     return flag[:int(n_live)]
 
 
-def kernel_value(kernel_id, kparams, v1, v2):
+def _table(table):
+    return None if table is None else _arr(table, np.float64)
+
+
+def kernel_value(kernel_id, kparams, v1, v2, table=None):
     kp = _arr(list(kparams) + [0.0] * (4 - len(kparams)), np.float64)
-    return float(lib().sdmo_kernel_value(kernel_id, _ptr(kp), v1, v2))
+    tb = _table(table)
+    return float(lib().sdmo_kernel_value(kernel_id, _ptr(kp), _ptr(tb), v1, v2))
 
 
-def coalescence_kernel(flag, volume, idx, n_live, kernel_id, kparams):
+def coalescence_kernel(flag, volume, idx, n_live, kernel_id, kparams, table=None):
     n = int(n_live)
     prob = np.zeros(max(n // 2, 1), np.float64)
     kp = _arr(list(kparams) + [0.0] * (4 - len(kparams)), np.float64)
+    tb = _table(table)
     lib().sdmo_coalescence_kernel(_ptr(prob), _ptr(_arr(flag, np.uint8)),
                                   _ptr(_arr(volume, np.float64)), _ptr(_arr(idx, np.uint32)),
-                                  n, kernel_id, _ptr(kp))
+                                  n, kernel_id, _ptr(kp), _ptr(tb))
     return prob[:n // 2]
 
 
@@ -231,7 +237,7 @@ def update_attributes(xi, attr, gamma, flag, idx, n_live, counters=None):
 
 
 def step(xi, attr, cell_id, n_cell, dv_per_cell, idx, n_live, *, dt, kernel_id, kparams,
-         seed, run, step, counters=None, want_gamma=False, want_flag=False):
+         seed, run, step, counters=None, want_gamma=False, want_flag=False, table=None):
     """One whole timestep (workflow figure, Steps 0-3) for one run.
 
     Returns a dict with the updated xi, attr, idx, n_live, cell_start,
@@ -253,6 +259,8 @@ def step(xi, attr, cell_id, n_cell, dv_per_cell, idx, n_live, *, dt, kernel_id, 
     for i in range(4):
         P.kparams[i] = kp[i]
     P.seed, P.run, P.step = seed, run, step
+    tb = _table(table)
+    P.table = _ptr(tb)
     gam = np.zeros(max(n_sd // 2, 1), np.float64) if want_gamma else None
     flg = np.zeros(max(n_sd, 1), np.uint8) if want_flag else None
     rc = lib().sdmo_step(_ptr(xi), _ptr(attr), int(attr.shape[0]), int(attr.shape[1]), n_sd,

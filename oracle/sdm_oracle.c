@@ -241,8 +241,24 @@ double sdmo_terminal_velocity(double r)
     return SDMO_VT_K3 * sqrt(r);
 }
 
+/* Cell of v in a tabulated kernel: the IEEE-754 bit pattern of v, as an
+ * unsigned 64-bit integer, shifted right by 52 - m, minus lo, clamped to
+ * [0, n - 1]. */
+static int64_t sdmo_table_cell(double v, int64_t lo, int64_t n, int m)
+{
+    uint64_t bits;
+    int64_t c;
+    memcpy(&bits, &v, sizeof bits);
+    c = (int64_t)(bits >> (52 - m)) - lo;
+    if (c < 0)
+        return 0;
+    if (c > n - 1)
+        return n - 1;
+    return c;
+}
+
 double sdmo_kernel_value(int32_t kernel_id, const double *kparams,
-                         double v1, double v2)
+                         const double *table, double v1, double v2)
 {
     switch (kernel_id) {
     case SDMO_KERNEL_GOLOVIN:
@@ -259,6 +275,13 @@ double sdmo_kernel_value(int32_t kernel_id, const double *kparams,
         return kparams[0];
     case SDMO_KERNEL_MULTIPLICATIVE:
         return kparams[0] * (v1 * v2);
+    case SDMO_KERNEL_TABULATED: {
+        int64_t lo = (int64_t)kparams[1], n = (int64_t)kparams[2];
+        int m = (int)kparams[3];
+        int64_t i1 = sdmo_table_cell(v1, lo, n, m), i2 = sdmo_table_cell(v2, lo, n, m);
+        int64_t r = i1 < i2 ? i1 : i2, c = i1 < i2 ? i2 : i1;
+        return kparams[0] * table[r * n + c];
+    }
     default:
         return 0.0;
     }
@@ -269,14 +292,14 @@ double sdmo_kernel_value(int32_t kernel_id, const double *kparams,
 void sdmo_coalescence_kernel(double *pair_prob, const uint8_t *flag,
                              const double *volume, const uint32_t *idx,
                              int64_t n_live, int32_t kernel_id,
-                             const double *kparams)
+                             const double *kparams, const double *table)
 {
     int64_t i;
     for (i = 0; i < n_live / 2; ++i)
         pair_prob[i] = 0.0;
     for (i = 0; i < n_live; ++i)
         if (flag[i])
-            pair_prob[i / 2] = sdmo_kernel_value(kernel_id, kparams,
+            pair_prob[i / 2] = sdmo_kernel_value(kernel_id, kparams, table,
                                                  volume[idx[i]], volume[idx[i + 1]]);
 }
 
@@ -430,7 +453,7 @@ int sdmo_step(uint64_t *xi, double *attr, int32_t n_attr, int64_t attr_stride,
     }
     sdmo_flag_pairs(flag, cell_id, cell_start, idx, n);
     /* step 2 */
-    sdmo_coalescence_kernel(prob, flag, attr, idx, n, p->kernel_id, p->kparams);
+    sdmo_coalescence_kernel(prob, flag, attr, idx, n, p->kernel_id, p->kparams, p->table);
     sdmo_times_max(prob, xi, flag, idx, n);
     sdmo_normalize(prob, p->dt, dv_per_cell, cell_id, cell_start, flag, idx, n);
     /* step 3 */

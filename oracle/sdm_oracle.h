@@ -34,7 +34,8 @@ enum { SDMO_STREAM_SHUFFLE = 0, SDMO_STREAM_GAMMA = 1, SDMO_STREAM_INIT = 2,
 
 /* Coalescence kernels a(v1, v2). */
 enum { SDMO_KERNEL_GOLOVIN = 0, SDMO_KERNEL_GEOMETRIC = 1,
-       SDMO_KERNEL_CONSTANT = 2, SDMO_KERNEL_MULTIPLICATIVE = 3 };
+       SDMO_KERNEL_CONSTANT = 2, SDMO_KERNEL_MULTIPLICATIVE = 3,
+       SDMO_KERNEL_TABULATED = 4 };
 
 /* Counter slots filled by sdmo_update_attributes (added to, never reset). */
 enum { SDMO_CNT_PAIRS = 0,      /* flagged pairs visited                    */
@@ -89,12 +90,17 @@ void     sdmo_flag_pairs(uint8_t *flag, const int32_t *cell_id,
 /* ---- Step 2: collision probability, eq. (3) -----------------------------
  * Pair slot of the pair opened at flagged position i is floor(i/2); slots
  * [0, floor(n_live/2)) that no flagged position maps to hold 0.          */
+/* Kernels: GOLOVIN kp[0](v1+v2); GEOMETRIC (the gravitational kernel);
+ * CONSTANT kp[0]; MULTIPLICATIVE kp[0] v1 v2; TABULATED kp[0] times the
+ * caller's table entry T[min(i1,i2)][max(i1,i2)] (table: n*n row-major),
+ * i(v) = (bit pattern of v >> (52 - m)) - lo clamped to [0, n-1], with
+ * lo = kp[1], n = kp[2], m = kp[3]; table is NULL for the other kernels. */
 double   sdmo_kernel_value(int32_t kernel_id, const double *kparams,
-                           double v1, double v2);
+                           const double *table, double v1, double v2);
 void     sdmo_coalescence_kernel(double *pair_prob, const uint8_t *flag,
                                  const double *volume, const uint32_t *idx,
                                  int64_t n_live, int32_t kernel_id,
-                                 const double *kparams);
+                                 const double *kparams, const double *table);
 void     sdmo_times_max(double *pair_prob, const uint64_t *xi,
                         const uint8_t *flag, const uint32_t *idx,
                         int64_t n_live);
@@ -125,6 +131,7 @@ typedef struct {
     uint64_t seed;
     uint32_t run;
     uint32_t step;
+    const double *table;   /* TABULATED kernel only */
 } sdmo_params;
 
 int      sdmo_step(uint64_t *xi, double *attr, int32_t n_attr,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsdm.so")
 
 SDM_OK = 0
 STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP = range(5)
-KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE = range(4)
+KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE, KERNEL_TABULATED = range(5)
 CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2, CNT_FALLBACK = range(6)
 N_COUNTERS = 8
 
@@ -31,7 +31,8 @@ class SdmError(RuntimeError):
 
 
 class Kernel(C.Structure):
-    _fields_ = [("id", C.c_int32), ("reserved", C.c_int32), ("p", C.c_double * 4)]
+    _fields_ = [("id", C.c_int32), ("reserved", C.c_int32), ("p", C.c_double * 4),
+                ("table", C.c_void_p)]
 
 
 class Rng(C.Structure):
@@ -166,12 +167,15 @@ def _stream(stream=None):
     return s.cuda_stream
 
 
-def kernel(kernel_id, params=(0.0,)):
+def kernel(kernel_id, params=(0.0,), table=None):
+    """An sdm_kernel; table: device tensor of float64 (tabulated kernels),
+    which the caller keeps alive while the kernel is in use."""
     k = Kernel()
     k.id = int(kernel_id)
     p = list(params) + [0.0] * (4 - len(params))
     for i in range(4):
         k.p[i] = float(p[i])
+    k.table = _ptr(table)
     return k
 
 
@@ -382,14 +386,15 @@ class Context:
 class Batch:
     """A batch of independent runs advanced together (sdm_batch_*).
 
-    segments: list of (offset, n_sd, dv, kernel_id, kparams, run)."""
+    segments: list of (offset, n_sd, dv, kernel_id, kparams, run[, table])."""
 
     def __init__(self, ctx, segments):
         self.ctx = ctx
         arr = (Segment * len(segments))()
-        for i, (off, n, dv, kid, kp, run) in enumerate(segments):
+        for i, seg in enumerate(segments):
+            off, n, dv, kid, kp, run = seg[:6]
             arr[i].offset, arr[i].n_sd, arr[i].dv = int(off), int(n), float(dv)
-            arr[i].kernel = kernel(kid, kp)
+            arr[i].kernel = kernel(kid, kp, seg[6] if len(seg) > 6 else None)
             arr[i].run = int(run)
         self.n_seg = len(segments)
         self._h = C.c_void_p()

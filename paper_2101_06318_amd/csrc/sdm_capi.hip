@@ -82,11 +82,46 @@ static int check_state(const sdm_ctx *ctx, const sdm_state *st, const sdm_step_p
         REQUIRE(((uintptr_t)st->xi & 15) == 0, "xi must be 16-byte aligned");
     }
     REQUIRE(p->dv_per_cell || p->dv > 0, "need dv_per_cell or dv > 0");
-    REQUIRE(p->kernel.id >= SDM_KERNEL_GOLOVIN && p->kernel.id <= SDM_KERNEL_MULTIPLICATIVE,
-            "unknown kernel id %d", p->kernel.id);
+    if (int rc = check_kernel(p->kernel, "kernel"))
+        return rc;
     REQUIRE(std::isfinite(p->dt) && p->dt >= 0, "dt invalid");
     return SDM_OK;
 }
+
+namespace sdm {
+
+int check_kernel(const sdm_kernel &k, const char *what)
+{
+    if (k.id < SDM_KERNEL_GOLOVIN || k.id > SDM_KERNEL_TABULATED)
+        return fail(SDM_E_INVALID, "%s: unknown kernel id %d", what, k.id);
+    if (k.id == SDM_KERNEL_TABULATED) {
+        const double n = k.p[2], m = k.p[3], lo = k.p[1];
+        if (!k.table)
+            return fail(SDM_E_INVALID, "%s: tabulated kernel without a table", what);
+        if (!(n >= 1 && n <= 4096 && n == std::floor(n)))
+            return fail(SDM_E_INVALID, "%s: table size p[2] must be an integer in [1, 4096]",
+                        what);
+        if (!(m >= 0 && m <= 12 && m == std::floor(m)))
+            return fail(SDM_E_INVALID, "%s: cells per octave p[3] must be 2^m, m in [0, 12]",
+                        what);
+        if (!(lo >= 0 && lo < 4096.0 * 4096.0 && lo == std::floor(lo)))
+            return fail(SDM_E_INVALID, "%s: first cell code p[1] invalid", what);
+    }
+    return SDM_OK;
+}
+
+KernelDesc kernel_desc(const sdm_kernel &k)
+{
+    KernelDesc d{};
+    d.id = k.id;
+    d.reserved = 0;
+    for (int i = 0; i < 4; ++i)
+        d.p[i] = k.p[i];
+    d.table = k.id == SDM_KERNEL_TABULATED ? k.table : nullptr;
+    return d;
+}
+
+}  // namespace sdm
 
 extern "C" {
 
@@ -203,9 +238,7 @@ int sdm_step(sdm_ctx *ctx, const sdm_state *st, const sdm_step_params *p, hipStr
     in.dt = p->dt;
     in.dv_cell = p->dv_per_cell;
     in.dv = p->dv;
-    in.kern.id = p->kernel.id;
-    for (int i = 0; i < 4; ++i)
-        in.kern.p[i] = p->kernel.p[i];
+    in.kern = kernel_desc(p->kernel);
     in.idx_out = st->idx;
     in.cell_start = st->cell_start;
     in.n_live_out = st->n_live_dev;
@@ -297,8 +330,8 @@ int sdm_batch_create(sdm_ctx *ctx, sdm_batch **b, const sdm_segment *segs, int32
                 "not overlap the previous segment", i);
         REQUIRE(g.n_sd >= 0 && g.offset + g.n_sd <= ctx->n_sd_max, "segment %d: size", i);
         REQUIRE(g.dv > 0 && std::isfinite(g.dv), "segment %d: dv", i);
-        REQUIRE(g.kernel.id >= SDM_KERNEL_GOLOVIN && g.kernel.id <= SDM_KERNEL_MULTIPLICATIVE,
-                "segment %d: kernel id", i);
+        if (int rc = check_kernel(g.kernel, "segment kernel"))
+            return rc;
         end = g.offset + g.n_sd;
     }
     sdm_batch *nb = nullptr;

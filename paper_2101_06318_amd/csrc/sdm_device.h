@@ -77,13 +77,22 @@ __device__ __forceinline__ uint64_t uniform_to_key(double u)
 
 // ------------------------------------------------------------- kernels
 enum { KERNEL_GOLOVIN = 0, KERNEL_GEOMETRIC = 1, KERNEL_CONSTANT = 2,
-       KERNEL_MULTIPLICATIVE = 3 };
+       KERNEL_MULTIPLICATIVE = 3, KERNEL_TABULATED = 4 };
 
 struct KernelDesc {
     int32_t id;
     int32_t reserved;
     double p[4];
+    const double *table;  // KERNEL_TABULATED: n x n, row-major
 };
+
+// Cell of volume v in a tabulated kernel: the IEEE pattern of v shifted
+// right by 52 - m, less lo, clamped to [0, n - 1] (integer operations only).
+__device__ __forceinline__ int64_t table_cell(double v, int64_t lo, int64_t n, int m)
+{
+    const int64_t c = (int64_t)((uint64_t)__double_as_longlong(v) >> (52 - m)) - lo;
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
 
 #define SDM_PI_D 3.141592653589793
 
@@ -144,6 +153,13 @@ __device__ __forceinline__ double kernel_value(const KernelDesc &k, double v1,
         return k.p[0];
     case KERNEL_MULTIPLICATIVE:
         return k.p[0] * (v1 * v2);
+    case KERNEL_TABULATED: {
+        const int64_t lo = (int64_t)k.p[1], n = (int64_t)k.p[2];
+        const int m = (int)k.p[3];
+        const int64_t i1 = table_cell(v1, lo, n, m), i2 = table_cell(v2, lo, n, m);
+        const int64_t a = i1 < i2 ? i1 : i2, b = i1 < i2 ? i2 : i1;
+        return k.p[0] * k.table[a * n + b];
+    }
     default:
         return 0.0;
     }

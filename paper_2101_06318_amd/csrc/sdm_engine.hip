@@ -708,6 +708,8 @@ struct PairCtx {
     double norm;         // (dt / dV_c) * F(n_c)
     int32_t kid;         // kernel id
     double kp;           // kernel parameter p[0]
+    double kq[3];        // p[1..3] and the table (tabulated kernels)
+    const double *table;
     uint32_t run;
     uint32_t slot_base;  // rank from which slots are numbered
     uint32_t gbase;      // offset of the run's slots in gamma_out
@@ -723,12 +725,18 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
         const int ki = a.seg_kernel[c];
         pc.kid = a.kernels[ki].id;
         pc.kp = a.kernels[ki].p[0];
+        for (int i = 0; i < 3; ++i)
+            pc.kq[i] = a.kernels[ki].p[i + 1];
+        pc.table = a.kernels[ki].table;
         pc.run = (uint32_t)a.seg_run[c];
         pc.gbase = a.seg_off[c] >> 1;
     } else {
         dvc = a.dv_cell ? a.dv_cell[c] : a.dv;
         pc.kid = a.kern.id;
         pc.kp = a.kern.p[0];
+        for (int i = 0; i < 3; ++i)
+            pc.kq[i] = a.kern.p[i + 1];
+        pc.table = a.kern.table;
         pc.run = a.run;
         pc.gbase = 0;
     }
@@ -745,7 +753,10 @@ __device__ __forceinline__ double pair_prob(const PairCtx &pc, uint64_t xa, doub
     kd.id = pc.kid;
     kd.reserved = 0;
     kd.p[0] = pc.kp;
-    kd.p[1] = kd.p[2] = kd.p[3] = 0.0;
+    kd.p[1] = pc.kq[0];
+    kd.p[2] = pc.kq[1];
+    kd.p[3] = pc.kq[2];
+    kd.table = pc.table;
     const double ak = kernel_value(kd, va, vb);
     const uint64_t xm = xa > xb ? xa : xb;
     return (ak * (double)xm) * pc.norm;
@@ -1861,10 +1872,7 @@ Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64
             run[c] = (int32_t)segs[c].run;
             dv[c] = segs[c].dv;
             kidx[c] = c;
-            kernels[c].id = segs[c].kernel.id;
-            kernels[c].reserved = 0;
-            for (int i = 0; i < 4; ++i)
-                kernels[c].p[i] = segs[c].kernel.p[i];
+            kernels[c] = kernel_desc(segs[c].kernel);
         }
         off[C] = (uint32_t)n_items;
         p->seg_off = upload(p, off);

@@ -176,6 +176,12 @@ struct sdm_ctx {
 
 namespace sdm {
 
+// Coalescence kernel descriptors (sdm_capi.hip): check_kernel validates an
+// sdm_kernel on the host (returns SDM_OK or a failure with a message naming
+// `what`); kernel_desc copies it for the device.
+int check_kernel(const sdm_kernel &k, const char *what);
+KernelDesc kernel_desc(const sdm_kernel &k);
+
 // engine entry points (sdm_engine.hip)
 Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
                double expected_per_cell);

@@ -355,24 +355,6 @@ static int noalloc_scratch(uint32_t **out)
     return SDM_OK;
 }
 
-static int check_kernel(const sdm_kernel *k)
-{
-    if (!k)
-        return fail(SDM_E_INVALID, "kernel is NULL");
-    if (k->id < SDM_KERNEL_GOLOVIN || k->id > SDM_KERNEL_MULTIPLICATIVE)
-        return fail(SDM_E_INVALID, "unknown kernel id %d", k->id);
-    return SDM_OK;
-}
-
-static KernelDesc to_desc(const sdm_kernel *k)
-{
-    KernelDesc d{};
-    d.id = k->id;
-    for (int i = 0; i < 4; ++i)
-        d.p[i] = k->p[i];
-    return d;
-}
-
 extern "C" {
 
 int sdm_urand(sdm_ctx *ctx, double *u01, int64_t n, const sdm_rng *rng, uint32_t stream_id,
@@ -491,9 +473,10 @@ static int pair_rate_common(sdm_ctx *ctx, double *pair_prob, int which, const ui
 {
     KernelDesc kd{};
     if (which & PR_KERNEL) {
-        if (int rc = check_kernel(k))
+        REQUIRE(k, "kernel is NULL");
+        if (int rc = check_kernel(*k, "kernel"))
             return rc;
-        kd = to_desc(k);
+        kd = kernel_desc(*k);
         REQUIRE(volume, "volume is NULL");
     }
     if (which & PR_MAX)
