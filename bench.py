@@ -15,6 +15,8 @@ Workloads (--workload, default box):
   ensemble   1024 independent boxes of 2^8..2^16 SDs (log-uniform), Golovin
              and gravitational kernels alternating, advanced together
              (sdm_batch_step) with the autotuned schedule.
+             --n-attr K adds K - 1 passive extensive attribute rows (chemistry
+             as an extension, Sec. 5; 16 in the sub-results).
   golovin    the paper's validation run itself: the box with 2^13 SDs for
              3600 steps from its initial state, 16 seeds, each timed as graph
              replays of 1200 steps; mean moments at 1200, 2400 and 3600 s
@@ -275,7 +277,10 @@ def cpu_line(value, unit, seconds, core, host, sample):
 def bench_box(args, sdm, torch, np, workloads):
     n_sd = 1 << args.log2_n_sd
     w = workloads.box(n_sd, seed=2)
-    ctx = sdm.Context(n_sd, 1, 1)
+    n_attr = getattr(args, "n_attr", 1)
+    if n_attr > 1:
+        w = workloads.with_extra_attributes(w, n_attr)
+    ctx = sdm.Context(n_sd, 1, n_attr)
     st = sdm.State(w["xi"], w["attr"], None, 1)
     k = sdm.kernel(w["kernel_id"], w["kparams"])
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -297,15 +302,20 @@ def bench_box(args, sdm, torch, np, workloads):
     f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
     assert ctx.read_errors() == 0
     # per pair: xi and v of two SDs (32 B) read, their Index entries written
-    # and read back (16 B); xi and v of both written back on a collision
-    # (32 B): 48 + 32 f_coll
-    b_alg = algorithmic_bytes(pairs, f_coll, 48.0, 32.0)
+    # and read back (16 B); on a collision the other attribute rows of both
+    # read (16 (n_attr - 1) B) and xi and every row of both written back
+    # (16 + 16 n_attr B): 48 + 32 n_attr f_coll
+    b_alg = algorithmic_bytes(pairs, f_coll, 48.0, 32.0 * n_attr)
     workload = "golovin_box_2_%d" % args.log2_n_sd
+    if n_attr > 1:
+        workload += "_%d_attributes" % n_attr
     step_ms = gms if gms else total_ms / K
-    out = base_line("SDM pair-steps/s at n_sd=2^%d" % args.log2_n_sd,
+    out = base_line("SDM pair-steps/s at n_sd=2^%d" % args.log2_n_sd +
+                    (", %d attributes" % n_attr if n_attr > 1 else ""),
                     (n_sd // 2) / (step_ms / 1e3), "pair-steps/s", K, args.warmup,
                     step_ms, "f64",
-                    {"workload": workload, "n_sd": n_sd, "cells": 1, "kernel": "golovin",
+                    {"workload": workload, "n_sd": n_sd, "n_attr": n_attr, "cells": 1,
+                     "kernel": "golovin",
                      "b_per_s": w["b"], "dt_s": w["dt"], "dv_m3": float(w["dv"][0]), "seed": 2,
                      "timing": TIMING if gms else TIMING_EAGER,
                      "n_live": int(st.n_live.item()), "collision_fraction": f_coll})
@@ -821,6 +831,9 @@ def main():
     ap.add_argument("--workload", default="box",
                     choices=["box", "grid", "ensemble", "golovin", "surrogate", "train"])
     ap.add_argument("--log2-n-sd", type=int, default=22)
+    ap.add_argument("--n-attr", type=int, default=1,
+                    help="box: attribute rows per SD (row 0 the volume, the others passive "
+                         "extensive attributes)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time given to the oracle baseline (whole steps, at least one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -875,7 +888,12 @@ def sub_results(args, sdm, torch, np, workloads):
     `--workload X` gives each its own line with one)."""
     import copy
     res = {}
-    for name, fn in (("grid", bench_grid), ("ensemble", bench_ensemble),
+    def box16(a, *rest):
+        a.n_attr = 16
+        return bench_box(a, *rest)
+
+    for name, fn in (("box_16_attributes", box16), ("grid", bench_grid),
+                     ("ensemble", bench_ensemble),
                      ("golovin", bench_golovin), ("surrogate", bench_surrogate),
                      ("train", bench_train)):
         a = copy.copy(args)

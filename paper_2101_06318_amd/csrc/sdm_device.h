@@ -343,6 +343,19 @@ __device__ __forceinline__ void collide_attr(double &Aj, double &Ak, uint64_t g,
         Aj = merged;
 }
 
+// Attribute rows r0 .. n_attr - 1 of a colliding pair.
+__device__ __forceinline__ void collide_rows(double *attr, int r0, int n_attr, int64_t stride,
+                                             uint32_t sj, uint32_t sk, uint64_t g, bool split)
+{
+    for (int r = r0; r < n_attr; ++r) {
+        double *A = attr + (int64_t)r * stride;
+        double Aj = A[sj], Ak = A[sk];
+        collide_attr(Aj, Ak, g, split);
+        A[sj] = Aj;
+        A[sk] = Ak;
+    }
+}
+
 // Writes the outcome of a pair with g > 0 to the global state.
 __device__ __forceinline__ void apply_collision(const Collision &c, uint32_t sa,
                                                 uint32_t sb, uint64_t *xi,
@@ -353,13 +366,7 @@ __device__ __forceinline__ void apply_collision(const Collision &c, uint32_t sa,
     const uint32_t sk = c.a_is_j ? sb : sa;
     xi[sj] = c.xj_new;
     xi[sk] = c.xk_new;
-    for (int r = 0; r < n_attr; ++r) {
-        double *A = attr + (int64_t)r * stride;
-        double Aj = A[sj], Ak = A[sk];
-        collide_attr(Aj, Ak, c.g, c.split);
-        A[sj] = Aj;
-        A[sk] = Ak;
-    }
+    collide_rows(attr, 0, n_attr, stride, sj, sk, c.g, c.split);
 }
 
 // apply_collision for a caller that holds the pair's volumes (attribute
@@ -377,13 +384,8 @@ __device__ __forceinline__ void apply_collision_v(const Collision &c, uint32_t s
     collide_attr(Vj, Vk, c.g, c.split);
     attr[sj] = Vj;
     attr[sk] = Vk;
-    for (int r = 1; r < n_attr; ++r) {
-        double *A = attr + (int64_t)r * stride;
-        double Aj = A[sj], Ak = A[sk];
-        collide_attr(Aj, Ak, c.g, c.split);
-        A[sj] = Aj;
-        A[sk] = Ak;
-    }
+    if (n_attr > 1)
+        collide_rows(attr, 1, n_attr, stride, sj, sk, c.g, c.split);
 }
 
 // Inclusive scan over the 64 lanes of a wave on DPP operands (no LDS trip):

@@ -707,9 +707,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
 struct PairCtx {
     double norm;         // (dt / dV_c) * F(n_c)
     int32_t kid;         // kernel id
+    int32_t kidx;        // the cell's entry of the batch kernel table
     double kp;           // kernel parameter p[0]
-    double kq[3];        // p[1..3] and the table (tabulated kernels)
-    const double *table;
     uint32_t run;
     uint32_t slot_base;  // rank from which slots are numbered
     uint32_t gbase;      // offset of the run's slots in gamma_out
@@ -724,19 +723,15 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
         dvc = a.seg_dv[c];
         const int ki = a.seg_kernel[c];
         pc.kid = a.kernels[ki].id;
+        pc.kidx = ki;
         pc.kp = a.kernels[ki].p[0];
-        for (int i = 0; i < 3; ++i)
-            pc.kq[i] = a.kernels[ki].p[i + 1];
-        pc.table = a.kernels[ki].table;
         pc.run = (uint32_t)a.seg_run[c];
         pc.gbase = a.seg_off[c] >> 1;
     } else {
         dvc = a.dv_cell ? a.dv_cell[c] : a.dv;
         pc.kid = a.kern.id;
+        pc.kidx = 0;
         pc.kp = a.kern.p[0];
-        for (int i = 0; i < 3; ++i)
-            pc.kq[i] = a.kern.p[i + 1];
-        pc.table = a.kern.table;
         pc.run = a.run;
         pc.gbase = 0;
     }
@@ -745,18 +740,23 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
     return pc;
 }
 
-// p of eq. (3) in the order kernel, times max xi, times (dt/dV) F(n).
-__device__ __forceinline__ double pair_prob(const PairCtx &pc, uint64_t xa, double va,
-                                            uint64_t xb, double vb)
+// p of eq. (3) in the order kernel, times max xi, times (dt/dV) F(n).  The
+// kernel's whole descriptor is read only for tabulated kernels (their table
+// and grid); the others need p[0] alone.
+template <class Args>
+__device__ __forceinline__ double pair_prob(const Args &a, const PairCtx &pc, uint64_t xa,
+                                            double va, uint64_t xb, double vb)
 {
     KernelDesc kd;
-    kd.id = pc.kid;
-    kd.reserved = 0;
-    kd.p[0] = pc.kp;
-    kd.p[1] = pc.kq[0];
-    kd.p[2] = pc.kq[1];
-    kd.p[3] = pc.kq[2];
-    kd.table = pc.table;
+    if (pc.kid == KERNEL_TABULATED) {
+        kd = a.seg_run ? a.kernels[pc.kidx] : a.kern;
+    } else {
+        kd.id = pc.kid;
+        kd.reserved = 0;
+        kd.p[0] = pc.kp;
+        kd.p[1] = kd.p[2] = kd.p[3] = 0.0;
+        kd.table = nullptr;
+    }
     const double ak = kernel_value(kd, va, vb);
     const uint64_t xm = xa > xb ? xa : xb;
     return (ak * (double)xm) * pc.norm;
@@ -929,7 +929,7 @@ __device__ void group_outputs(const GroupArgs &a, int g, int b0, int nb, uint32_
             sb_[u] = get.s(f + 1);
             xb[u] = get.xi(f + 1);
             const double vb = get.v(f + 1);
-            pv[u] = pair_prob(pc, xa[u], va, xb[u], vb);
+            pv[u] = pair_prob(a, pc, xa[u], va, xb[u], vb);
         }
         double phi[2] = {0.0, 0.0};
         if (valid[0] && valid[1] && (qv[0] & 1u) == 0u && qv[1] == qv[0] + 1 &&
@@ -1489,7 +1489,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             const double va = a.attr[sa], vb = a.attr[sb2];
             const double phi =
                 word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
-            const double p = pair_prob(pc, xa, va, xb, vb);
+            const double p = pair_prob(a, pc, xa, va, xb, vb);
             finish_pair_v(a, pc, q, p, phi, sa, xa, va, sb2, xb, vb, st);
         }
         if (a.counters)
@@ -1600,7 +1600,7 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
                 const uint32_t q = (op.rank - pc.slot_base) >> 1;
                 const uint64_t xo = a.xi[op.s], xc = a.xi[cl.s];
                 const double vo = a.attr[op.s], vc = a.attr[cl.s];
-                const double p = pair_prob(pc, xo, vo, xc, vc);
+                const double p = pair_prob(a, pc, xo, vo, xc, vc);
                 const double phi =
                     word_to_uniform(philox_word(a.seed, pc.run, step, SDM_STREAM_GAMMA, q));
                 finish_pair_v(a, pc, q, p, phi, op.s, xo, vo, cl.s, xc, vc, st);

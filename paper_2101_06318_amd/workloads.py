@@ -75,6 +75,19 @@ def grid(seed: int = 3, nx: int = 128, ny: int = 128, mean_per_cell: float = 64.
                 counts=counts)
 
 
+def with_extra_attributes(w: dict, n_attr: int, seed: int = 11):
+    """The workload w with attribute rows added up to n_attr in total: row i
+    >= 1 beyond w's own is a passive extensive attribute (for example the
+    amount of a chemical species a droplet carries), volume times a
+    lognormal per-droplet concentration (sigma_g 2, seed-drawn)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = w["attr"][0]
+    rows = [w["attr"][i] for i in range(w["attr"].shape[0])]
+    while len(rows) < n_attr:
+        rows.append(v * np.exp(np.log(2.0) * rng.standard_normal(v.shape[0])))
+    return dict(w, attr=np.stack(rows[:n_attr]).astype(np.float64))
+
+
 def ensemble(seed: int = 4, n_runs: int = 1024, log2_min: float = 8.0,
              log2_max: float = 16.0, dt: float = 1.0, n_sd_override=None):
     """Batched ensemble of independent boxes: run r has
