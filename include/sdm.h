@@ -441,6 +441,43 @@ int sdm_mlp_adam(sdm_ctx *ctx, const sdm_mlp *w, const sdm_mlp_opt *opt, const f
 int sdm_hull_check(sdm_ctx *ctx, uint8_t *fallback, uint64_t *counters_dev, const float *x,
                    int64_t B, const float *lo, const float *hi, hipStream_t stream);
 
+/* Joint out-of-distribution test of the surrogate's inputs (a cell it
+ * cannot vouch for falls back to the particle method; Sec. 5 motivates a
+ * moments-only coupling): fallback[b] = 1 when any feature x[b][i] lies
+ * outside [lo[i], hi[i]] or is NaN, or, with an occupancy grid, when the
+ * cell of (x[b][0], x[b][1], x[b][2]) holds no training input: cell index
+ * k_i = floor((x[b][i] - glo[i]) * ginv[i]) clamped to [0, G - 1] (single
+ * precision, in this order), occ[(k_0 G + k_1) G + k_2] != 0 for cells the
+ * training inputs reached.  lo, hi: host float[5]; glo, ginv: host float[3]
+ * (copied); occ: device uint8[G^3] or NULL (box only), 1 <= G <= 256.
+ * counters_dev (optional) gets the number of fallback rows. */
+int sdm_ood_check(sdm_ctx *ctx, uint8_t *fallback, uint64_t *counters_dev, const float *x,
+                  int64_t B, const float *lo, const float *hi, const uint8_t *occ, int32_t G,
+                  const float *glo, const float *ginv, hipStream_t stream);
+
+/* The surrogate's fallback: particles rebuilt from a cell's moments, to be
+ * advanced by the particle method (sdm_batch_step with one segment of
+ * n_per_cell slots per cell) and measured again (sdm_moments).  For cell c
+ * with select[c] != 0 (select NULL: every cell) and M0, M1, M2 > 0, slots
+ * [c n, c n + n) (n = n_per_cell) receive n SDs at the standard-normal
+ * quantiles z_i = sqrt(2) erfinv(2 (i + 1/2)/n - 1): volumes e^(sigma z_i)
+ * scaled to the mean volume M1/M0, sigma chosen so that the SDs' own
+ * M2 M0 / M1^2 equals the cell's (60 bisection steps; the set holds at
+ * most n times the squared mean, so larger ratios are capped), every
+ * multiplicity rint(M0 dv / n), at least 1: the cell's M0 up to that
+ * rounding, M1 and M2 exactly.  Other cells' slots get multiplicity 0 and
+ * volume 0.  M: device double[n_cell][3] (per unit volume, sdm_moments
+ * layout); xi: device uint64[n_cell n]; v: device double[n_cell n]
+ * (attribute row 0). */
+int sdm_seed_from_moments(sdm_ctx *ctx, uint64_t *xi, double *v, const double *M,
+                          const uint8_t *select, int32_t n_cell, int32_t n_per_cell, double dv,
+                          hipStream_t stream);
+
+/* M[c] = M_src[c] (all three moments) for cells with select[c] != 0.
+ * M, M_src: device double[n][3]; select: device uint8[n]. */
+int sdm_moments_merge(sdm_ctx *ctx, double *M, const double *M_src, const uint8_t *select,
+                      int64_t n, hipStream_t stream);
+
 /* Surrogate input of n cells: x[c] = ((log M0, log M1, log M2, dt,
  * kernel_id) - mean) / std with M: device double[n][3] (sdm_moments
  * layout), x: device float[n][5]; mean, std: host float[5] (copied). */

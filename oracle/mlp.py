@@ -194,3 +194,100 @@ def apply(M, y, fallback, dt, mean, std):
     keep = np.ones(len(M), bool) if fallback is None else (np.asarray(fallback) == 0)
     M[keep] = new[keep]
     return M
+
+
+def ood_fallback(x, lo, hi, occ=None, glo=None, ginv=None):
+    """Joint out-of-distribution test: the per-feature box (hull_fallback)
+    and, given an occupancy grid occ [G][G][G] over the first three
+    features, 1 where the row's cell holds no training input.  Cell index
+    k_i = floor((x_i - glo_i) * ginv_i) in float32 (subtraction, then
+    product), clamped to [0, G - 1]."""
+    x = np.asarray(x, np.float32)
+    out = hull_fallback(x, lo, hi)
+    if occ is None:
+        return out
+    occ = np.asarray(occ)
+    G = occ.shape[0]
+    t = (x[:, :3] - np.asarray(glo, np.float32)) * np.asarray(ginv, np.float32)
+    t = np.nan_to_num(t, nan=0.0)           # NaN rows fall back through the box test
+    k = np.clip(np.floor(t).astype(np.int64), 0, G - 1)
+    empty = occ[k[:, 0], k[:, 1], k[:, 2]] == 0
+    return np.where(out == 1, 1, empty.astype(np.uint8)).astype(np.uint8)
+
+
+def occupancy(x, lo, hi, G):
+    """Occupancy grid of standardised training inputs x [n][5] over their
+    first three features: G cells per axis spanning [lo_i, hi_i]; returns
+    (occ [G][G][G] uint8, glo float32[3], ginv float32[3]) with
+    ginv = G / (hi - lo) in float32."""
+    lo3 = np.asarray(lo, np.float32)[:3]
+    hi3 = np.asarray(hi, np.float32)[:3]
+    span = np.where(hi3 > lo3, hi3 - lo3, np.float32(1.0)).astype(np.float32)
+    ginv = (np.float32(G) / span).astype(np.float32)
+    t = (np.asarray(x, np.float32)[:, :3] - lo3) * ginv
+    k = np.clip(np.floor(t).astype(np.int64), 0, G - 1)
+    occ = np.zeros((G, G, G), np.uint8)
+    occ[k[:, 0], k[:, 1], k[:, 2]] = 1
+    return occ, lo3, ginv
+
+
+def seed_from_moments(M, select, n, dv):
+    """Particles of each cell rebuilt from its moments (the surrogate's
+    fallback to the particle method).  A selected cell with positive M0,
+    M1, M2 (per unit volume) gets n SDs at the standard-normal quantiles
+    z_i = sqrt(2) erfinv(2 (i + 1/2)/n - 1): volumes exp(sigma z_i) scaled
+    to the mean volume M1/M0, where sigma solves
+    R(sigma) = n sum exp(2 sigma z) / (sum exp(sigma z))^2 = M2 M0 / M1^2
+    (R is 1 at sigma = 0 and grows towards n): 60 halvings of [0, hi], hi
+    the first of 1, 2, 4, ..., 64 with R(hi) >= the target.  Multiplicities
+    rint(M0 dv / n), at least 1.  Other cells: multiplicity 0 and volume 0.
+    Returns xi [n_cell n] uint64 and v [n_cell n]."""
+    from scipy.special import erfinv
+    M = np.asarray(M, np.float64)
+    nc = len(M)
+    xi = np.zeros(nc * n, np.uint64)
+    v = np.zeros(nc * n, np.float64)
+    z = [math.sqrt(2.0) * float(erfinv(2.0 * ((i + 0.5) / n) - 1.0)) for i in range(n)]
+
+    def ratio(sg):
+        S1 = S2 = 0.0
+        for zi in z:            # summed in slot order
+            e = math.exp(sg * zi)
+            S1 += e
+            S2 += e * e
+        return (n * S2) / (S1 * S1)
+
+    for c in range(nc):
+        M0, M1, M2 = (float(a) for a in M[c])
+        if (select is not None and not select[c]) or not (M0 > 0 and M1 > 0 and M2 > 0):
+            continue
+        m1 = M1 / M0
+        target = (M2 / M0) / (m1 * m1)
+        sg = 0.0
+        if target > 1.0 and n > 1:
+            lo, hi = 0.0, 1.0
+            while hi < 64.0 and ratio(hi) < target:
+                hi *= 2.0
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                if ratio(mid) < target:
+                    lo = mid
+                else:
+                    hi = mid
+            sg = 0.5 * (lo + hi)
+        e = [math.exp(sg * zi) for zi in z]
+        S = 0.0
+        for ei in e:
+            S += ei
+        scale = (m1 * n) / S
+        v[c * n:(c + 1) * n] = [ei * scale for ei in e]
+        xi[c * n:(c + 1) * n] = np.uint64(max(1.0, float(np.rint(M0 * dv / n))))
+    return xi, v
+
+
+def moments_merge(M, M_src, select):
+    """M[c] = M_src[c] for selected cells."""
+    M = np.array(M, np.float64, copy=True)
+    sel = np.asarray(select) != 0
+    M[sel] = np.asarray(M_src, np.float64)[sel]
+    return M

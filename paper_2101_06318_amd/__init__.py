@@ -118,6 +118,9 @@ SIGNATURES = {
     "sdm_hull_check": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "sdm_mlp_features": (_INT, [_P, _P, _P, _I64, _D, _I32, _P, _P, _P]),
     "sdm_mlp_apply": (_INT, [_P, _P, _P, _P, _I64, _D, _P, _P, _P]),
+    "sdm_ood_check": (_INT, [_P, _P, _P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P]),
+    "sdm_seed_from_moments": (_INT, [_P, _P, _P, _P, _P, _I32, _I32, _D, _P]),
+    "sdm_moments_merge": (_INT, [_P, _P, _P, _P, _I64, _P]),
 }
 
 MLP_N_PARAMS = 34179
@@ -326,6 +329,31 @@ class Context:
         hi_a = (C.c_float * 5)(*[float(v) for v in hi])
         _check(lib().sdm_hull_check(self._h, _ptr(fallback), _ptr(counters), _ptr(x),
                                     int(x.shape[0]), lo_a, hi_a, _stream(stream)))
+
+    def ood_check(self, fallback, x, lo, hi, occ=None, glo=None, ginv=None, counters=None,
+                  stream=None):
+        """Joint out-of-distribution test (box + occupancy grid of
+        G = round(occ.numel() ** (1/3)) cells per axis)."""
+        lo_a = (C.c_float * 5)(*[float(v) for v in lo])
+        hi_a = (C.c_float * 5)(*[float(v) for v in hi])
+        G = 0
+        glo_a = ginv_a = None
+        if occ is not None:
+            G = int(round(occ.numel() ** (1.0 / 3.0)))
+            glo_a = (C.c_float * 3)(*[float(v) for v in glo])
+            ginv_a = (C.c_float * 3)(*[float(v) for v in ginv])
+        _check(lib().sdm_ood_check(self._h, _ptr(fallback), _ptr(counters), _ptr(x),
+                                   int(x.shape[0]), lo_a, hi_a, _ptr(occ), G, glo_a, ginv_a,
+                                   _stream(stream)))
+
+    def seed_from_moments(self, xi, v, M, select, n_per_cell, dv, stream=None):
+        _check(lib().sdm_seed_from_moments(self._h, _ptr(xi), _ptr(v), _ptr(M), _ptr(select),
+                                           int(M.shape[0]), int(n_per_cell), float(dv),
+                                           _stream(stream)))
+
+    def moments_merge(self, M, M_src, select, stream=None):
+        _check(lib().sdm_moments_merge(self._h, _ptr(M), _ptr(M_src), _ptr(select),
+                                       int(M.shape[0]), _stream(stream)))
 
     def mlp_features(self, x, M, dt, kernel_id, mean, std, stream=None):
         m_a = (C.c_float * 5)(*[float(v) for v in mean])

@@ -25,6 +25,8 @@
 // sums are reduced in a fixed order by a second kernel (deterministic).
 #include <math.h>
 
+#include <cmath>
+
 #include "sdm_internal.h"
 
 using namespace sdm;
@@ -740,6 +742,133 @@ __global__ void k_hull(uint8_t *__restrict__ fb, unsigned long long *__restrict_
     }
 }
 
+// Joint test: the per-feature box, then the cell of an occupancy grid over
+// the first three features (the standardised log moments), G cells per axis
+// from glo with G / (ghi - glo) cells per unit (ginv): a row whose cell no
+// training input reached is out of distribution.  Single-precision steps
+// in a fixed order, so the host's reading of the same rule agrees.
+struct OodArgs {
+    float lo[5], hi[5];
+    float glo[3], ginv[3];
+    int32_t G;
+};
+
+__global__ void k_ood(uint8_t *__restrict__ fb, unsigned long long *__restrict__ counters,
+                      const float *__restrict__ x, int64_t B, const uint8_t *__restrict__ occ,
+                      OodArgs o)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int out = 0;
+    if (b < B) {
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            const float v = x[b * NIN + i];
+            if (!(v >= o.lo[i] && v <= o.hi[i]))
+                out = 1;
+        }
+        if (!out && occ) {
+            int64_t cell = 0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float t = (x[b * NIN + i] - o.glo[i]) * o.ginv[i];
+                int k = (int)floorf(t);
+                k = k < 0 ? 0 : (k >= o.G ? o.G - 1 : k);  // the box's upper edge
+                cell = cell * o.G + k;
+            }
+            out = occ[cell] == 0;
+        }
+        fb[b] = (uint8_t)out;
+    }
+    if (counters) {
+        const int c = __syncthreads_count(out);
+        if (threadIdx.x == 0 && c > 0)
+            atomicAdd(counters + SDM_CNT_FALLBACK, (unsigned long long)c);
+    }
+}
+
+// Fallback of the surrogate: the particles of a cell rebuilt from its
+// moments.  Cell c (when selected) gets n SDs in slots [c n, c n + n) at the
+// standard-normal quantiles z_i = sqrt(2) erfinv(2 (i + 1/2)/n - 1):
+// v_i = e^(sigma z_i) scaled so that the mean volume is M1/M0, with sigma
+// the root of R(sigma) = n sum e^(2 sigma z_i) / (sum e^(sigma z_i))^2 =
+// M2 M0 / M1^2 (the sample's own second moment, matched exactly; R grows
+// from 1 at sigma = 0 towards n), found by 60 bisection steps on
+// [0, hi], hi the first of 1, 2, 4, .. 64 with R(hi) >= the target;
+// multiplicity rint(M0 dV / n), at least 1.  Unselected cells and cells
+// without positive moments get multiplicity 0 (no live SDs).  The slots'
+// volumes hold the z_i while sigma is sought.
+__device__ __forceinline__ double seed_ratio(const double *z, int n, double sg)
+{
+    double S1 = 0.0, S2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double e = exp(sg * z[i]);
+        S1 += e;
+        S2 += e * e;
+    }
+    return ((double)n * S2) / (S1 * S1);
+}
+
+__global__ void k_seed(uint64_t *__restrict__ xi, double *__restrict__ v,
+                       const double *__restrict__ M, const uint8_t *__restrict__ sel,
+                       int32_t n_cell, int32_t n, double dv)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cell)
+        return;
+    const int64_t base = c * (int64_t)n;
+    double *vc = v + base;
+    const double M0 = M[c * 3 + 0], M1 = M[c * 3 + 1], M2 = M[c * 3 + 2];
+    if ((sel && !sel[c]) || !(M0 > 0.0 && M1 > 0.0 && M2 > 0.0)) {
+        for (int i = 0; i < n; ++i) {
+            xi[base + i] = 0;
+            vc[i] = 0.0;
+        }
+        return;
+    }
+    const double m1 = M1 / M0;
+    const double target = (M2 / M0) / (m1 * m1);
+    for (int i = 0; i < n; ++i)
+        vc[i] = 1.4142135623730951 * erfinv(2.0 * (((double)i + 0.5) / (double)n) - 1.0);
+    double sg = 0.0;
+    if (target > 1.0 && n > 1) {
+        double lo = 0.0, hi = 1.0;
+        while (hi < 64.0 && seed_ratio(vc, n, hi) < target)
+            hi = hi * 2.0;
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (seed_ratio(vc, n, mid) < target)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        sg = 0.5 * (lo + hi);
+    }
+    double S = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double e = exp(sg * vc[i]);
+        vc[i] = e;
+        S += e;
+    }
+    const double scale = (m1 * (double)n) / S;
+    const double xr = rint((M0 * dv) / (double)n);
+    const uint64_t x = xr >= 1.0 ? (uint64_t)xr : 1ull;
+    for (int i = 0; i < n; ++i) {
+        vc[i] = vc[i] * scale;
+        xi[base + i] = x;
+    }
+}
+
+__global__ void k_merge(double *__restrict__ M, const double *__restrict__ src,
+                        const uint8_t *__restrict__ sel, int64_t n)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || !sel[c])
+        return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        M[c * 3 + k] = src[c * 3 + k];
+}
+
 struct Std5 {
     double mean[5], std[5];
 };
@@ -966,6 +1095,68 @@ int sdm_mlp_apply(sdm_ctx *ctx, double *M, const float *y, const uint8_t *fallba
     }
     hipLaunchKernelGGL(k_apply, dim3(grid_for(n, 256)), dim3(256), 0, stream, M, y, fallback, n,
                        dt, st);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_ood_check(sdm_ctx *ctx, uint8_t *fallback, uint64_t *counters_dev, const float *x,
+                  int64_t B, const float *lo, const float *hi, const uint8_t *occ, int32_t G,
+                  const float *glo, const float *ginv, hipStream_t stream)
+{
+    REQUIRE(ctx && lo && hi, "null ctx, lo or hi");
+    REQUIRE(B >= 0, "B < 0");
+    REQUIRE(!occ || (G >= 1 && G <= 256 && glo && ginv), "occupancy grid: G in [1, 256] "
+            "with glo and ginv");
+    if (B == 0)
+        return SDM_OK;
+    REQUIRE(fallback && x, "null fallback or x");
+    SDM_TRY
+    OodArgs o{};
+    for (int i = 0; i < NIN; ++i) {
+        o.lo[i] = lo[i];
+        o.hi[i] = hi[i];
+    }
+    if (occ) {
+        for (int i = 0; i < 3; ++i) {
+            o.glo[i] = glo[i];
+            o.ginv[i] = ginv[i];
+        }
+        o.G = G;
+    }
+    hipLaunchKernelGGL(k_ood, dim3(grid_for(B, 256)), dim3(256), 0, stream, fallback,
+                       (unsigned long long *)counters_dev, x, B, occ, o);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_seed_from_moments(sdm_ctx *ctx, uint64_t *xi, double *v, const double *M,
+                          const uint8_t *select, int32_t n_cell, int32_t n_per_cell, double dv,
+                          hipStream_t stream)
+{
+    REQUIRE(ctx, "null ctx");
+    REQUIRE(n_cell >= 0 && n_per_cell >= 1 && n_per_cell <= 1 << 20, "sizes out of range");
+    REQUIRE(dv > 0 && std::isfinite(dv), "dv must be positive");
+    if (n_cell == 0)
+        return SDM_OK;
+    REQUIRE(xi && v && M, "null xi, v or M");
+    SDM_TRY
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(n_cell, 64)), dim3(64), 0, stream, xi, v, M,
+                       select, n_cell, n_per_cell, dv);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_moments_merge(sdm_ctx *ctx, double *M, const double *M_src, const uint8_t *select,
+                      int64_t n, hipStream_t stream)
+{
+    REQUIRE(ctx, "null ctx");
+    REQUIRE(n >= 0, "n < 0");
+    if (n == 0)
+        return SDM_OK;
+    REQUIRE(M && M_src && select, "null M, M_src or select");
+    SDM_TRY
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256)), dim3(256), 0, stream, M, M_src, select,
+                       n);
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }

@@ -98,6 +98,42 @@ def _lag_pairs(torch, hist, kid, lags, stride, dt):
     return out
 
 
+class ParticleFallback:
+    """The cells the surrogate cannot vouch for, advanced by the particle
+    method instead: each selected cell is rebuilt from its moments as
+    n_per_cell SDs (sdm_seed_from_moments), advanced by SDM steps as one
+    run of a batch (sdm_batch_step; run id = cell index), measured
+    (sdm_moments) and merged back into the moments (sdm_moments_merge).
+    Unselected cells carry no live SDs, so they cost only their slots."""
+
+    def __init__(self, n_cell, n_per_cell, dv, kernel_id, kparams, seed):
+        import torch
+        self.n_cell, self.n, self.dv, self.seed = n_cell, n_per_cell, float(dv), int(seed)
+        segs = [(c * n_per_cell, n_per_cell, self.dv, kernel_id, list(kparams), c)
+                for c in range(n_cell)]
+        n_sd = n_cell * n_per_cell
+        self.ctx = Context(n_sd, n_cell, 1)
+        self.st = State(np.zeros(n_sd, np.uint64), np.zeros((1, n_sd)), None, n_cell)
+        self.batch = Batch(self.ctx, segs)
+        self.M = torch.zeros((n_cell, 3), dtype=torch.float64, device="cuda")
+
+    def advance(self, M, select, dt, steps, step0, stream=None):
+        """M [n_cell][3] (device float64): the selected cells' moments after
+        `steps` particle steps of dt from their rebuilt particles; Philox
+        steps step0 .. step0 + steps - 1."""
+        c, st = self.ctx, self.st
+        c.seed_from_moments(st.xi, st.attr[0], M, select, self.n, self.dv, stream=stream)
+        for t in range(steps):
+            self.batch.step(st, dt, rng(self.seed, 0, step0 + t), stream=stream)
+        c.moments(self.M, st.xi, st.attr[0], st.idx, st.cell_start, self.n_cell, dv=self.dv,
+                  stream=stream)
+        c.moments_merge(M, self.M, select, stream=stream)
+
+    def close(self):
+        self.batch.close()
+        self.ctx.close()
+
+
 class Surrogate:
     """Trained network plus its input / target standardisation and hull."""
 
