@@ -620,40 +620,46 @@ def bench_golovin(args, sdm, torch, np, workloads):
 
 
 def bench_surrogate(args, sdm, torch, np, workloads):
-    """Surrogate step for every cell of the grid vs one SDM step of the grid
-    (static cells), both on the GPU; random-init weights (the arithmetic per
-    step does not depend on the weights)."""
+    """The moment surrogate for steps of 10 s: trained (replica means of the
+    particle method, the library's training kernels), judged against a
+    4096-member particle-method mean of 64 held-out grid cells at 600 s
+    (surrogate_gate), then its step (features, joint out-of-distribution
+    test, bf16 MFMA forward, update) timed on the 16384 cells of the grid
+    beside the particle method's step of the same grid (static cells)."""
+    from paper_2101_06318_amd import surrogate
+    m = 10
+    t0 = time.perf_counter()
+    ev, sur, sctx = surrogate.pipeline(torch, log=None, epochs=20, m=m)
+    pipe_s = time.perf_counter() - t0
     w = workloads.grid(seed=3)
     n_sd, n_cell = w["n_sd"], w["n_cell"]
     ctx = sdm.Context(n_sd, n_cell, 2)
     st = sdm.State(w["xi"], w["attr"], w["cell_id"], n_cell)
     dv = torch.as_tensor(np.asarray(w["dv"], np.float64)).cuda()
     k = sdm.kernel(w["kernel_id"], w["kparams"])
-    ctx.step(st, w["dt"], k, sdm.rng(3, 0, 0), dv_per_cell=dv)
-    M = torch.zeros((n_cell, 3), dtype=torch.float64, device="cuda")
-    ctx.moments(M, st.xi, st.attr[0], st.idx, st.cell_start, n_cell, dv_per_cell=dv)
-    torch.cuda.synchronize()
-    lm = torch.log(M).cpu().numpy()
-    mean = np.concatenate([lm.mean(0), [1.0, 1.0]]).astype(np.float32)
-    std = np.concatenate([lm.std(0) + 1e-6, [1.0, 1.0]]).astype(np.float32)
-    net = sdm.Mlp(ctx, workloads.mlp_init(7))
-    x = torch.zeros((n_cell, 5), dtype=torch.float32, device="cuda")
-    y = torch.zeros((n_cell, 3), dtype=torch.float32, device="cuda")
-    fb = torch.zeros(n_cell, dtype=torch.uint8, device="cuda")
-    lo, hi = [-8.0] * 5, [8.0] * 5
-    tm, ts = [0.0, 0.0, 0.0], [1e-6, 1e-9, 1e-6]
+    ctx.cell_sort(st.cell_start, st.idx, st.n_live, st.cell_id, n_cell)
+    M0 = torch.zeros((n_cell, 3), dtype=torch.float64, device="cuda")
+    ctx.moments(M0, st.xi, st.attr[0], st.idx, st.cell_start, n_cell, dv_per_cell=dv)
+    M = M0.clone()
+    bufs = sur.buffers(torch, n_cell)
+    counters = torch.zeros(8, dtype=torch.int64, device="cuda")
     lib = sdm.lib()
     e_fwd = [HipEvent(lib) for _ in range(2 * args.steps)]
 
-    def sur_step(t, stream, ev):
-        ctx.mlp_features(x, M, w["dt"], w["kernel_id"], mean, std, stream=stream)
-        ctx.hull_check(fb, x, lo, hi, stream=stream)
-        if ev is not None:
-            ev[0].record(stream)
-        ctx.mlp_forward(y, x, net, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-        ctx.mlp_apply(M, y, w["dt"], tm, ts, fallback=fb, stream=stream)
+    def sur_step(t, stream, ev_):
+        # the steps below are sur.step's calls, with events around the forward pass
+        c = sur.ctx
+        c.mlp_features(bufs["x"], M, m * w["dt"], w["kernel_id"], sur.x_mean, sur.x_std,
+                       stream=stream)
+        c.ood_check(bufs["fb"], bufs["x"], sur.lo, sur.hi, sur.occ, sur.glo, sur.ginv,
+                    counters=counters, stream=stream)
+        if ev_ is not None:
+            ev_[0].record(stream)
+        c.mlp_forward(bufs["y"], bufs["x"], sur.net, stream=stream)
+        if ev_ is not None:
+            ev_[1].record(stream)
+        c.mlp_apply(M, bufs["y"], m * w["dt"], sur.t_mean, sur.t_std, fallback=bufs["fb"],
+                    stream=stream)
 
     for t in range(args.warmup):
         sur_step(t, None, None)
@@ -661,6 +667,8 @@ def bench_surrogate(args, sdm, torch, np, workloads):
     stream = torch.cuda.Stream()
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
+    M.copy_(M0)
+    counters.zero_()
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         s0.record(stream)
@@ -669,7 +677,10 @@ def bench_surrogate(args, sdm, torch, np, workloads):
         s1.record(stream)
     torch.cuda.synchronize()
     sur_ms = s0.elapsed_time(s1)
-    fwd_ms = sum(e_fwd[2 * t].elapsed_ms(e_fwd[2 * t + 1]) for t in range(K)) / K
+    ood_rows = int(counters[5].item())
+    over = event_overhead_ms(torch, lib, stream)
+    fwd_ms = max(sum(e_fwd[2 * t].elapsed_ms(e_fwd[2 * t + 1]) for t in range(K)) / K - over,
+                 1e-6)
     for e in e_fwd:
         e.destroy()
     gms = None if args.eager else graph_ms(torch, sur_step, K, stream)
@@ -678,8 +689,8 @@ def bench_surrogate(args, sdm, torch, np, workloads):
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     r = sdm.rng(3, 0, 1, step_dev=step_dev)
 
-    def sdm_step(t, stream, ev):
-        ctx.step(st, w["dt"], k, r, stream=stream, events=ev, dv_per_cell=dv,
+    def sdm_step(t, stream, ev_):
+        ctx.step(st, w["dt"], k, r, stream=stream, events=ev_, dv_per_cell=dv,
                  step_advance=step_dev)
 
     for t in range(args.warmup):
@@ -693,34 +704,57 @@ def bench_surrogate(args, sdm, torch, np, workloads):
     out = base_line("surrogate cell-steps/s on the 128x128 grid", n_cell / (step_ms / 1e3),
                     "cell-steps/s", K, args.warmup, step_ms, "bf16",
                     {"workload": "surrogate_grid_128x128", "cells": n_cell,
-                     "network": "5-128-128-128-3 GELU", "dt_s": w["dt"], "seed": 3,
-                     "step": "features + hull test + forward + moment update",
+                     "network": "5-128-128-128-3 GELU", "surrogate_step_s": m * w["dt"],
+                     "sdm_dt_s": w["dt"], "seed": 3,
+                     "step": "features + joint OOD test + forward + moment update",
                      "timing": TIMING if gms else TIMING_EAGER})
     out["sdm_cell_steps_per_s"] = n_cell / (sdm_step_ms / 1e3)
     out["speedup_vs_sdm"] = out["value"] / out["sdm_cell_steps_per_s"]
+    # per simulated second: one surrogate step stands for m particle steps
+    out["speedup_per_simulated_second"] = m * out["speedup_vs_sdm"]
+    eq = ev.get("equivalent_members_m2")
+    out["surrogate_gate"] = {
+        "metric": "mean over 64 held-out cells of |M2_surrogate - M2_ref| / M2_ref at 600 s",
+        "m2_err": ev["err_surrogate"][2], "limit": 0.05, "met": bool(ev["gate_m2_5pct"]),
+        "m2_err_along_s": ev["err_m2_along"], "m0_err": ev["err_surrogate"][0],
+        "reference": "%d-member particle-method mean" % ev["members"],
+        "reference_m2_rel_se": ev["ref_rel_se"][2],
+        "single_sdm_run_m2_err": ev["err_single_sdm"][2],
+        "constant_tendency_m2_err": ev["err_constant_tendency"][2],
+        "domain_m2_err": ev["domain_err_surrogate"][2],
+        "equivalent_sdm_members_m2": eq,
+        "speedup_vs_equivalent_sdm_ensemble": (None if eq is None else
+                                               eq * out["speedup_per_simulated_second"]),
+        "fallback_fraction": ev["fallback_fraction"], "train_samples": ev["train_samples"],
+        "train_and_evaluate_s": round(pipe_s, 2)}
+    out["ood_fallback_rows_in_timing"] = ood_rows
     out["roofline"] = {"bound": "mfma", "kernel": "k_mlp_forward_split", "achieved": achieved,
                        "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None}
-    out["kernel_ms"] = {"k_mlp_forward_split": fwd_ms}
+    out["kernel_ms"] = {"k_mlp_forward_split": fwd_ms, "event_overhead_subtracted": over}
     out["graph_ms_per_step"] = gms
     out["eager_ms_per_step"] = sur_ms / K
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         from oracle import mlp
-        xh = x.cpu().numpy()
-        th = workloads.mlp_init(7)
-        net_o = mlp.Net("bf16")
-        reps = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < args.cpu_seconds:
-            net_o.forward(th, xh)
-            reps += 1
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": n_cell * reps / dt, "unit": "cell-steps/s",
-                               "cores": 1, "kind": "oracle", "seconds": round(dt, 3),
-                               "sample": "%d bf16-emulated forward passes over the 16384 cells "
-                                         "(numpy)" % reps}
+        xh = bufs["x"].cpu().numpy()
+        th = sur.net.params.cpu().numpy()
+
+        def sample(deadline):
+            net_o = mlp.Net("bf16")
+            reps = 0
+            t0_ = time.perf_counter()
+            while reps == 0 or time.perf_counter() < deadline:
+                net_o.forward(th, xh)
+                reps += 1
+            return reps, time.perf_counter() - t0_
+
+        (reps, dt_), core, host = host_oracle(sample, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_line(n_cell * reps / dt_, "cell-steps/s", dt_, core, host,
+                                       "%d bf16-emulated forward passes over the 16384 cells "
+                                       "(numpy, one core)" % reps)
     ctx.close()
+    sctx.close()
     return out
 
 

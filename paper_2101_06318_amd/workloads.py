@@ -75,6 +75,22 @@ def grid(seed: int = 3, nx: int = 128, ny: int = 128, mean_per_cell: float = 64.
                 counts=counts)
 
 
+def replicate_cells(w: dict, R: int, n_attr: int = 1):
+    """R independent copies of every cell of the grid workload w, as one
+    grid of R * n_cell cells: cell r * n_cell + c holds replica r of cell c
+    (the same SDs, so with the same initial state; the particle method's
+    random numbers, keyed by SD id, make the replicas independent
+    realisations).  Keeps the first n_attr attribute rows."""
+    n_cell = w["n_cell"]
+    xi = np.tile(w["xi"], R)
+    attr = np.tile(w["attr"][:n_attr], (1, R))
+    cell_id = (np.tile(w["cell_id"], R) +
+               np.repeat(np.arange(R, dtype=np.int64) * n_cell, w["n_sd"])).astype(np.int32)
+    return dict(w, n_sd=int(xi.shape[0]), n_cell=n_cell * R, xi=xi, attr=attr,
+                cell_id=cell_id, dv=np.tile(np.asarray(w["dv"], np.float64), R),
+                counts=np.tile(w["counts"], R), replicas=R, base_cells=n_cell)
+
+
 def with_extra_attributes(w: dict, n_attr: int, seed: int = 11):
     """The workload w with attribute rows added up to n_attr in total: row i
     >= 1 beyond w's own is a passive extensive attribute (for example the
