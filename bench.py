@@ -269,6 +269,41 @@ def oracle_box_sample(np, w, seed, deadline, cell_id_fn=None, n_cell=1):
     return npairs, steps, time.perf_counter() - t0
 
 
+def first_step_parity(sdm, torch, np, ctx, w, k, steps=2):
+    """Part of the oracle leg: the workload's first steps from its initial
+    state on the GPU (fresh state, slot gammas kept) against the oracle,
+    element by element; a gamma mismatch within 1e-12 of a threshold is a
+    counted flip, any other difference fails the run."""
+    import oracle
+    from tests.parity import compare_step, slot_probabilities
+    n = w["xi"].shape[0]
+    st = sdm.State(w["xi"], w["attr"], None, 1, want_gamma=True)
+    ref = dict(xi=w["xi"], attr=w["attr"], idx=np.arange(n, dtype=np.uint32), n_live=n)
+    flips = 0
+    for t in range(steps):
+        prev = ref
+        ctx.step(st, w["dt"], k, sdm.rng(2, 0, t), dv=w["dv"][0])
+        ref = oracle.step(prev["xi"], prev["attr"], None, 1, w["dv"], prev["idx"],
+                          prev["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
+                          kparams=w["kparams"], seed=2, run=0, step=t, want_gamma=True)
+        torch.cuda.synchronize()
+        nl = int(st.n_live.item())
+        got = dict(n_live=nl, xi=st.xi.cpu().numpy(), attr=st.attr.cpu().numpy(),
+                   idx=st.idx.cpu().numpy().view(np.uint32), gamma=st.gamma_out.cpu().numpy())
+
+        def pre(prev=prev, t=t):
+            return slot_probabilities(prev["xi"], prev["attr"], None, 1, w["dv"], prev["idx"],
+                                      prev["n_live"], dt=w["dt"], kernel_id=w["kernel_id"],
+                                      kparams=w["kparams"], seed=2, run=0, step=t)
+        f = compare_step(got, ref, pre, "step %d" % t)
+        flips += f
+        if f:
+            ref = dict(ref, xi=got["xi"], attr=got["attr"])
+    return {"steps": steps, "pairs_per_step": n // 2, "gamma_threshold_flips": flips,
+            "result": "bit-exact" if flips == 0 else "bit-exact except flipped pairs",
+            "against": "oracle (plain C, one thread)"}
+
+
 def cpu_line(value, unit, seconds, core, host, sample):
     return {"value": value, "unit": unit, "cores": 1, "kind": "oracle",
             "seconds": round(seconds, 3), "pinned_core": core, "host": host, "sample": sample}
@@ -325,6 +360,8 @@ def bench_box(args, sdm, torch, np, workloads):
     out["eager_ms_per_step"] = total_ms / K
     out["step_roofline"] = step_roofline(b_alg, step_ms)
     out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        out["parity_check"] = first_step_parity(sdm, torch, np, ctx, w, k)
     ctx.close()
     if not args.no_cpu_baseline:
         (npairs, steps, dt), core, host = host_oracle(
