@@ -539,6 +539,52 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     return out
 
 
+def bench_shuffles(args, sdm, torch, np, workloads):
+    """The per-cell permutation routines on the 128x128 grid (1.05e6 SDs in
+    16384 cells): sort by random keys (sdm_shuffle_per_cell, the GPU strategy
+    of Sec. 3.2), Fisher-Yates (one thread per cell) and MergeShuffle (one
+    launch per level), each from a scrambled Index; SDs permuted per second."""
+    w = workloads.grid(seed=3)
+    n, n_cell = w["n_sd"], w["n_cell"]
+    ctx = sdm.Context(n, n_cell, 1)
+    idx0 = torch.as_tensor(np.random.default_rng(1).permutation(n).astype(np.int32)).cuda()
+    idx = idx0.clone()
+    cs = torch.zeros(n_cell + 1, dtype=torch.int32, device="cuda")
+    nl = torch.tensor([n], dtype=torch.int64, device="cuda")
+    cid = torch.as_tensor(w["cell_id"]).cuda()
+    res = {}
+    for name, method in (("sort_by_random_key", 0), ("fisher_yates", 1), ("merge_shuffle", 2)):
+        def call(t):
+            r = sdm.rng(3, 0, t)
+            if method == 0:
+                ctx.shuffle_per_cell(cs, idx, nl, None, cid, n_cell, r=r)
+            else:
+                ctx.shuffle_variant(method, cs, idx, nl, cid, n_cell, r)
+        for t in range(3):
+            call(t)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        K = min(args.steps, 20)
+        e0.record()
+        for t in range(K):
+            call(t)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        res[name] = {"ms_per_call": ms, "sds_per_s": n / (ms / 1e3)}
+    ctx.close()
+    out = base_line("per-cell permutations on the 128x128 grid (SDs/s)",
+                    res["fisher_yates"]["sds_per_s"], "SDs/s", min(args.steps, 20), 3,
+                    res["fisher_yates"]["ms_per_call"], "u32",
+                    {"workload": "shuffle_grid_128x128", "n_sd": n, "cells": n_cell,
+                     "timing": "eager, CUDA events around K calls (cell sort included)"})
+    out["methods"] = res
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    return out
+
+
 def golovin_moments(t, N0, b, vbar):
     """Moments of the additive-kernel solution from an exponential start
     (eq. 7): M0 = N0 (1 - tau), M1 = N0 vbar, M2 = 2 N0 vbar^2 / (1 - tau)^2,
@@ -900,7 +946,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="box",
-                    choices=["box", "grid", "ensemble", "golovin", "surrogate", "train"])
+                    choices=["box", "grid", "ensemble", "golovin", "surrogate", "train",
+                             "shuffles"])
     ap.add_argument("--log2-n-sd", type=int, default=22)
     ap.add_argument("--n-attr", type=int, default=1,
                     help="box: attribute rows per SD (row 0 the volume, the others passive "
@@ -940,7 +987,7 @@ def main():
         del src, dst
     fn = {"box": bench_box, "grid": bench_grid, "ensemble": bench_ensemble,
           "golovin": bench_golovin, "surrogate": bench_surrogate,
-          "train": bench_train}[args.workload]
+          "train": bench_train, "shuffles": bench_shuffles}[args.workload]
     out = fn(args, sdm, torch, np, workloads)
     if args.workload == "box" and not args.no_sub:
         out["sub_results"] = sub_results(args, sdm, torch, np, workloads)
@@ -951,7 +998,7 @@ SUB_KEYS = ("metric", "value", "unit", "ms_per_step", "dtype", "config", "kernel
             "roofline", "step_roofline", "cell_steps_per_s", "sdm_cell_steps_per_s",
             "speedup_vs_sdm", "default_schedule", "golovin_moments_16_seeds",
             "golovin_within_tolerance", "golovin_tolerance", "wall_s_3600_steps",
-            "surrogate_gate")
+            "surrogate_gate", "methods")
 
 
 def sub_results(args, sdm, torch, np, workloads):
@@ -966,7 +1013,7 @@ def sub_results(args, sdm, torch, np, workloads):
     for name, fn in (("box_16_attributes", box16), ("grid", bench_grid),
                      ("ensemble", bench_ensemble),
                      ("golovin", bench_golovin), ("surrogate", bench_surrogate),
-                     ("train", bench_train)):
+                     ("train", bench_train), ("shuffles", bench_shuffles)):
         a = copy.copy(args)
         a.no_cpu_baseline = True
         a.steps = min(args.steps, 100)

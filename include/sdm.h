@@ -199,6 +199,33 @@ int sdm_shuffle_per_cell(sdm_ctx *ctx, uint32_t *cell_start, uint32_t *idx,
                          const double *u01_by_sd, const sdm_rng *rng,
                          hipStream_t stream);
 
+/* The O(n) permutations of each cell that Sec. 3.2 names besides sorting
+ * by random keys: the serial permutation of the CPU backend (Fisher-Yates,
+ * after Appendix A of the original SDM paper) and MergeShuffle (Bacher et
+ * al. 2015), which parallelises within a cell.  idx[0:n_live] is first
+ * cell-sorted stably (as sdm_cell_sort), then each cell's segment, in that
+ * order, is permuted in place.  A random integer uniform in [0, m) is
+ * floor(U m) = (w m) >> 53, w the 53-bit word of U(rng, stream, element).
+ *  SDM_SHUFFLE_FISHER_YATES: for i = n-1 down to 1 (n the cell's size),
+ *    k uniform in [0, i] (stream 5, element = global position cs + i),
+ *    swap the cell's positions i and k.
+ *  SDM_SHUFFLE_MERGE: Fisher-Yates (as above) on blocks of 16 positions
+ *    from the cell's start; then for d = 1, 2, ... the blocks of 16 2^(d-1)
+ *    are merged pairwise, [s, m) with [m, e), e = min(s + 16 2^d, cell
+ *    end): i = s, j = m; repeat { coin = top bit of the word of (stream
+ *    8 + 2d, element i); coin 0: stop if i == j; coin 1: stop if j == e,
+ *    else swap i and j, j += 1; i += 1 }; then for each remaining i < e: k
+ *    uniform in [0, i - s] (stream 9 + 2d, element i), swap i and s + k.
+ *    Elements are global positions.
+ * Both give uniformly random permutations (pinned by exact enumeration and
+ * frequency tests) but not the permutation of sdm_shuffle_per_cell.  Fisher-
+ * Yates runs one thread per cell; MergeShuffle one launch per level.  Same
+ * arguments as sdm_cell_sort plus the method and the random numbers. */
+enum { SDM_SHUFFLE_FISHER_YATES = 1, SDM_SHUFFLE_MERGE = 2 };
+int sdm_shuffle_variant(sdm_ctx *ctx, int32_t method, uint32_t *cell_start, uint32_t *idx,
+                        const int64_t *n_live_dev, const int32_t *cell_id, int32_t n_cell,
+                        const sdm_rng *rng, hipStream_t stream);
+
 /* flag_pairs (PairIndicator, Sec. 3.1; GPU listing Fig. 3):
  * pair_flag[i] = i+1 < n_live && cell(idx[i+1]) == cell(idx[i]) &&
  *                (i - cell_start[cell(idx[i])]) even.

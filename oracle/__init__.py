@@ -26,7 +26,8 @@ _LIB = os.path.join(_HERE, "libsdmo.so")
 _lock = threading.Lock()
 _lib = None
 
-STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP = range(5)
+STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP, STREAM_FY = range(6)
+STREAM_MERGE = 8
 KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE, KERNEL_TABULATED = range(5)
 CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2 = range(5)
 N_COUNTERS = 8
@@ -80,6 +81,8 @@ def _declare(L):
         "sdmo_cell_sort": (C.c_int, [_P, _P, _I64, _P, _I32]),
         "sdmo_shuffle_per_cell": (C.c_int, [_P, _P, _I64, _P, _I32, _P]),
         "sdmo_flag_pairs": (None, [_P, _P, _P, _P, _I64]),
+        "sdmo_shuffle_fisher_yates": (C.c_int, [_P, _P, _I64, _P, _I32, _U64, _U32, _U32]),
+        "sdmo_shuffle_merge": (C.c_int, [_P, _P, _I64, _P, _I32, _U64, _U32, _U32]),
         "sdmo_kernel_value": (_D, [_I32, _P, _P, _D, _D]),
         "sdmo_coalescence_kernel": (None, [_P, _P, _P, _P, _I64, _I32, _P, _P]),
         "sdmo_times_max": (None, [_P, _P, _P, _P, _I64]),
@@ -180,6 +183,20 @@ def flag_pairs(cell_id, cell_start, idx, n_live):
 
 def _table(table):
     return None if table is None else _arr(table, np.float64)
+
+
+def shuffle_variant(method, idx, n_live, cell_id, n_cell, seed, run, step):
+    """The O(n) per-cell permutations (Sec. 3.2): method "fisher_yates" or
+    "merge"; returns (idx, cell_start)."""
+    n = int(n_live)
+    out = _arr(idx, np.uint32).copy()
+    cs = np.zeros(n_cell + 1, np.uint32)
+    cid = np.zeros(max(len(out), 1), np.int32) if cell_id is None else _arr(cell_id, np.int32)
+    fn = {"fisher_yates": lib().sdmo_shuffle_fisher_yates,
+          "merge": lib().sdmo_shuffle_merge}[method]
+    if fn(_ptr(cs), _ptr(out), n, _ptr(cid), int(n_cell), int(seed), int(run), int(step)):
+        raise ValueError("cell id out of range")
+    return out[:n], cs
 
 
 def kernel_value(kernel_id, kparams, v1, v2, table=None):

@@ -140,6 +140,90 @@ int sdmo_cell_sort(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
     return 0;
 }
 
+/* Uniform integer in [0, m) from the 53-bit word of element e. */
+static uint64_t draw_below(uint64_t seed, uint32_t run, uint32_t step, uint32_t stream,
+                           uint64_t e, uint64_t m)
+{
+    uint64_t w = sdmo_word(seed, run, step, stream, e) >> 11;
+    return (uint64_t)(((unsigned __int128)w * m) >> 53);
+}
+
+static void swap_u32(uint32_t *a, uint32_t *b)
+{
+    uint32_t t = *a;
+    *a = *b;
+    *b = t;
+}
+
+/* Fisher-Yates on positions [s, e) of idx, draws keyed by position. */
+static void fisher_yates(uint32_t *idx, int64_t s, int64_t e, uint64_t seed, uint32_t run,
+                         uint32_t step)
+{
+    int64_t i;
+    for (i = e - 1; i > s; --i) {
+        uint64_t k = draw_below(seed, run, step, SDMO_STREAM_FY, (uint64_t)i,
+                                (uint64_t)(i - s + 1));
+        swap_u32(&idx[i], &idx[s + (int64_t)k]);
+    }
+}
+
+int sdmo_shuffle_fisher_yates(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
+                              const int32_t *cell_id, int32_t n_cell, uint64_t seed,
+                              uint32_t run, uint32_t step)
+{
+    int32_t c;
+    if (sdmo_cell_sort(cell_start, idx, n_live, cell_id, n_cell))
+        return -1;
+    for (c = 0; c < n_cell; ++c)
+        fisher_yates(idx, cell_start[c], cell_start[c + 1], seed, run, step);
+    return 0;
+}
+
+/* One merge of MergeShuffle at level d: [s, m) and [m, e) are shuffled. */
+static void merge_shuffled(uint32_t *idx, int64_t s, int64_t m, int64_t e, int d,
+                           uint64_t seed, uint32_t run, uint32_t step)
+{
+    int64_t i = s, j = m;
+    for (;;) {
+        uint64_t coin = sdmo_word(seed, run, step, SDMO_STREAM_MERGE + 2 * d, (uint64_t)i) >> 63;
+        if (coin == 0) {
+            if (i == j)
+                break;
+        } else {
+            if (j == e)
+                break;
+            swap_u32(&idx[i], &idx[j]);
+            ++j;
+        }
+        ++i;
+    }
+    for (; i < e; ++i) {
+        uint64_t k = draw_below(seed, run, step, SDMO_STREAM_MERGE + 2 * d + 1, (uint64_t)i,
+                                (uint64_t)(i - s + 1));
+        swap_u32(&idx[i], &idx[s + (int64_t)k]);
+    }
+}
+
+int sdmo_shuffle_merge(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
+                       const int32_t *cell_id, int32_t n_cell, uint64_t seed, uint32_t run,
+                       uint32_t step)
+{
+    int32_t c;
+    if (sdmo_cell_sort(cell_start, idx, n_live, cell_id, n_cell))
+        return -1;
+    for (c = 0; c < n_cell; ++c) {
+        int64_t cs = cell_start[c], ce = cell_start[c + 1], s, w;
+        int d;
+        for (s = cs; s < ce; s += 16)
+            fisher_yates(idx, s, s + 16 < ce ? s + 16 : ce, seed, run, step);
+        for (d = 1, w = 16; cs + w < ce; ++d, w *= 2)
+            for (s = cs; s + w < ce; s += 2 * w)
+                merge_shuffled(idx, s, s + w, s + 2 * w < ce ? s + 2 * w : ce, d, seed, run,
+                               step);
+    }
+    return 0;
+}
+
 typedef struct {
     int32_t  cell;
     uint32_t s;

@@ -30,7 +30,8 @@ extern "C" {
 
 /* Random streams (which Philox counter word 2 selects). */
 enum { SDMO_STREAM_SHUFFLE = 0, SDMO_STREAM_GAMMA = 1, SDMO_STREAM_INIT = 2,
-       SDMO_STREAM_REASSIGN = 3, SDMO_STREAM_MLP = 4 };
+       SDMO_STREAM_REASSIGN = 3, SDMO_STREAM_MLP = 4, SDMO_STREAM_FY = 5,
+       SDMO_STREAM_MERGE = 8 };
 
 /* Coalescence kernels a(v1, v2). */
 enum { SDMO_KERNEL_GOLOVIN = 0, SDMO_KERNEL_GEOMETRIC = 1,
@@ -77,6 +78,27 @@ int64_t  sdmo_remove_if_equal_0(uint32_t *idx, int64_t n_live,
  * Both return 0, or -1 if a cell id lies outside [0, n_cell).            */
 int      sdmo_cell_sort(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
                         const int32_t *cell_id, int32_t n_cell);
+/* The O(n) permutations of each cell (Sec. 3.2: the serial permutation
+ * of the CPU backend, MergeShuffle for parallelism), applied to the live
+ * SDs of each cell in their incoming order after a stable cell sort.
+ * Random integer k uniform in [0, m): floor(U m) = (w m) >> 53 with w the
+ * 53-bit word of U, exact in 128-bit integers.
+ *  Fisher-Yates: for i = n-1 down to 1, k from draw (stream FY, element =
+ *    the position cs + i), swap positions i and k of the cell.
+ *  MergeShuffle: blocks of 16 positions from the cell's start get
+ *    Fisher-Yates; then levels d = 1, 2, ...: blocks of 16 2^(d-1) are
+ *    merged pairwise ([s, m) with [m, e), e = min(s + 16 2^d, cell end))
+ *    by: i = s, j = m; repeat { coin = top bit of the draw (stream
+ *    MERGE + 2d, element i); coin 0: stop if i == j; coin 1: stop if
+ *    j == e, else swap i and j, j += 1; then i += 1 }; then for i < e:
+ *    k uniform in [0, i - s] (stream MERGE + 2d + 1, element i), swap i and
+ *    s + k.  Elements are global positions.  Returns -1 on a bad cell id. */
+int      sdmo_shuffle_fisher_yates(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
+                                   const int32_t *cell_id, int32_t n_cell, uint64_t seed,
+                                   uint32_t run, uint32_t step);
+int      sdmo_shuffle_merge(uint32_t *cell_start, uint32_t *idx, int64_t n_live,
+                            const int32_t *cell_id, int32_t n_cell, uint64_t seed,
+                            uint32_t run, uint32_t step);
 int      sdmo_shuffle_per_cell(uint32_t *cell_start, uint32_t *idx,
                                int64_t n_live, const int32_t *cell_id,
                                int32_t n_cell, const double *u01_by_sd);

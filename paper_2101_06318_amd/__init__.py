@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsdm.so")
 SDM_OK = 0
 STREAM_SHUFFLE, STREAM_GAMMA, STREAM_INIT, STREAM_REASSIGN, STREAM_MLP = range(5)
 KERNEL_GOLOVIN, KERNEL_GEOMETRIC, KERNEL_CONSTANT, KERNEL_MULTIPLICATIVE, KERNEL_TABULATED = range(5)
+SHUFFLE_FISHER_YATES, SHUFFLE_MERGE = 1, 2
 CNT_PAIRS, CNT_COLLISIONS, CNT_CAPPED, CNT_ZEROED, CNT_GAMMA_GE2, CNT_FALLBACK = range(6)
 N_COUNTERS = 8
 
@@ -92,6 +93,7 @@ SIGNATURES = {
     "sdm_cell_sort": (_INT, [_P, _P, _P, _P, _P, _I32, _P]),
     "sdm_shuffle_per_cell": (_INT, [_P, _P, _P, _P, _P, _P, _I32, _P, C.POINTER(Rng), _P]),
     "sdm_flag_pairs": (_INT, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "sdm_shuffle_variant": (_INT, [_P, _I32, _P, _P, _P, _P, _I32, C.POINTER(Rng), _P]),
     "sdm_coalescence_kernel": (_INT, [_P, _P, _P, _P, _P, _P, C.POINTER(Kernel), _P]),
     "sdm_times_max": (_INT, [_P, _P, _P, _P, _P, _P, _P]),
     "sdm_normalize": (_INT, [_P, _P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -241,6 +243,12 @@ class Context:
     def remove_if_equal_0(self, idx, n_live, xi, stream=None):
         _check(lib().sdm_remove_if_equal_0(self._h, _ptr(idx), _ptr(n_live), _ptr(xi),
                                            _stream(stream)))
+
+    def shuffle_variant(self, method, cell_start, idx, n_live, cell_id, n_cell, r,
+                        stream=None):
+        _check(lib().sdm_shuffle_variant(self._h, int(method), _ptr(cell_start), _ptr(idx),
+                                         _ptr(n_live), _ptr(cell_id), int(n_cell), C.byref(r),
+                                         _stream(stream)))
 
     def cell_sort(self, cell_start, idx, n_live, cell_id, n_cell, stream=None):
         _check(lib().sdm_cell_sort(self._h, _ptr(cell_start), _ptr(idx), _ptr(n_live),

@@ -295,6 +295,108 @@ __global__ void k_reassign(int32_t *cell_id, int64_t n_sd, int32_t n_cell, uint6
         cell_id[e + 1] = (int32_t)(word_to_uniform(w.odd) * (double)n_cell);
 }
 
+// ------------------------------------------------ O(n) permutations
+// The per-cell permutations the paper names besides sorting by random keys
+// (Sec. 3.2): the serial O(n) permutation of its CPU backend (Fisher-Yates)
+// and MergeShuffle.  Both permute each cell's segment of a cell-sorted
+// Index in place; every random draw is the Philox word of its global
+// position in a stream of its own, so results do not depend on the launch.
+constexpr uint32_t STREAM_FY = 5;
+constexpr uint32_t STREAM_MERGE = 8;
+constexpr int MERGE_BLOCK = 16;
+
+// Uniform integer in [0, m): floor(U m) = (w m) >> 53, w the 53-bit word.
+__device__ __forceinline__ uint64_t draw_below(uint64_t seed, uint32_t run, uint32_t step,
+                                               uint32_t stream, uint64_t e, uint64_t m)
+{
+    const uint64_t w = philox_word(seed, run, step, stream, e) >> 11;
+    return __umul64hi(w << 11, m);
+}
+
+__device__ __forceinline__ void fy_range(uint32_t *idx, int64_t s, int64_t e, uint64_t seed,
+                                         uint32_t run, uint32_t step)
+{
+    for (int64_t i = e - 1; i > s; --i) {
+        const int64_t k =
+            s + (int64_t)draw_below(seed, run, step, STREAM_FY, (uint64_t)i, (uint64_t)(i - s + 1));
+        const uint32_t a = idx[i], b = idx[k];
+        idx[i] = b;
+        idx[k] = a;
+    }
+}
+
+// Cell containing sorted position p: largest c with cell_start[c] <= p.
+__device__ __forceinline__ int cell_of_position(const uint32_t *cs, int n_cell, uint32_t p)
+{
+    int lo = 0, hi = n_cell;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cs[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_fisher_yates(uint32_t *idx, const uint32_t *cs, int n_cell, uint64_t seed,
+                               uint32_t run, uint32_t step, const uint32_t *step_dev)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cell)
+        return;
+    fy_range(idx, cs[c], cs[c + 1], seed, run, step_of(step, step_dev));
+}
+
+// Level 0: Fisher-Yates on every block of MERGE_BLOCK positions from a
+// cell's start.  Level d >= 1: the pairwise merges of blocks of
+// MERGE_BLOCK 2^(d-1) positions.  One thread per position; the thread at a
+// block (or merge) start does it.
+__global__ void k_merge_level(uint32_t *idx, const uint32_t *cs, int n_cell, const int64_t *n_live,
+                              int d, uint64_t seed, uint32_t run, uint32_t step,
+                              const uint32_t *step_dev)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *n_live)
+        return;
+    const int c = cell_of_position(cs, n_cell, (uint32_t)p);
+    const int64_t c0 = cs[c], c1 = cs[c + 1];
+    const uint32_t t = step_of(step, step_dev);
+    if (d == 0) {
+        if ((p - c0) % MERGE_BLOCK == 0)
+            fy_range(idx, p, min(p + MERGE_BLOCK, c1), seed, run, t);
+        return;
+    }
+    const int64_t w = (int64_t)MERGE_BLOCK << (d - 1);
+    if ((p - c0) % (2 * w) != 0 || p + w >= c1)
+        return;
+    const int64_t s = p, m = p + w, e = min(p + 2 * w, c1);
+    const uint32_t sc = STREAM_MERGE + 2u * (uint32_t)d;
+    int64_t i = s, j = m;
+    for (;;) {
+        const uint64_t coin = philox_word(seed, run, t, sc, (uint64_t)i) >> 63;
+        if (coin == 0) {
+            if (i == j)
+                break;
+        } else {
+            if (j == e)
+                break;
+            const uint32_t a = idx[i], b = idx[j];
+            idx[i] = b;
+            idx[j] = a;
+            ++j;
+        }
+        ++i;
+    }
+    for (; i < e; ++i) {
+        const int64_t k = s + (int64_t)draw_below(seed, run, t, sc + 1u, (uint64_t)i,
+                                                  (uint64_t)(i - s + 1));
+        const uint32_t a = idx[i], b = idx[k];
+        idx[i] = b;
+        idx[k] = a;
+    }
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -448,6 +550,35 @@ int sdm_shuffle_per_cell(sdm_ctx *ctx, uint32_t *cell_start, uint32_t *idx,
     engine_run(ctx, p, in, stream);
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks_for(ctx->n_sd_max, TPB)), dim3(TPB), 0, stream,
                        idx, ctx->tmp_u32, n_live_dev);
+    SDM_HIP(hipGetLastError());
+    SDM_CATCH
+}
+
+int sdm_shuffle_variant(sdm_ctx *ctx, int32_t method, uint32_t *cell_start, uint32_t *idx,
+                        const int64_t *n_live_dev, const int32_t *cell_id, int32_t n_cell,
+                        const sdm_rng *rng, hipStream_t stream)
+{
+    REQUIRE(method == SDM_SHUFFLE_FISHER_YATES || method == SDM_SHUFFLE_MERGE,
+            "unknown shuffle method %d", method);
+    REQUIRE(rng, "rng is NULL");
+    REQUIRE(ctx && cell_start && idx && n_live_dev, "null argument");
+    REQUIRE(ctx->n_sd_max <= ((int64_t)1 << 32), "positions must fit the Philox element word");
+    if (int rc = sdm_cell_sort(ctx, cell_start, idx, n_live_dev, cell_id, n_cell, stream))
+        return rc;
+    SDM_TRY
+    if (method == SDM_SHUFFLE_FISHER_YATES) {
+        hipLaunchKernelGGL(k_fisher_yates, dim3(blocks_for(n_cell, 64)), dim3(64), 0, stream, idx,
+                           cell_start, n_cell, rng->seed, rng->run, rng->step, rng->step_dev);
+    } else {
+        // levels until a block spans the largest possible cell
+        int levels = 1;
+        while (((int64_t)MERGE_BLOCK << (levels - 1)) < ctx->n_sd_max)
+            ++levels;
+        for (int d = 0; d < levels; ++d)
+            hipLaunchKernelGGL(k_merge_level, dim3(blocks_for(ctx->n_sd_max, TPB)), dim3(TPB), 0,
+                               stream, idx, cell_start, n_cell, n_live_dev, d, rng->seed,
+                               rng->run, rng->step, rng->step_dev);
+    }
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }
