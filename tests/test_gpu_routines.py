@@ -246,3 +246,54 @@ def test_invalid_calls_raise(sdm, ctx):
     with pytest.raises(sdm.SdmError):
         ctx.cell_sort(zeros(2, torch.int32), zeros(4, torch.int32),
                       dev(np.array([4], np.int64)), zeros(4, torch.int32), 10 ** 6)
+
+
+@pytest.mark.parametrize("n_sd,n_cell", [(1 << 21, 1), (1049600, 16384)])
+def test_list_routines_at_full_size(sdm, n_sd, n_cell):
+    """sdm_cell_sort and sdm_shuffle_per_cell (inline keys) at the sizes of
+    the box and the grid: every entry of the Index and of cell_start."""
+    import torch
+    big = sdm.Context(n_sd, n_cell, 1)
+    cid, idx = _cells(n_sd, n_cell, 13)
+    n_live = n_sd - 17
+    for routine in ("cell_sort", "shuffle"):
+        d_idx, d_cs = dev(idx), zeros(n_cell + 1, torch.int32)
+        nl = dev(np.array([n_live], np.int64))
+        if routine == "cell_sort":
+            big.cell_sort(d_cs, d_idx, nl, dev(cid), n_cell)
+            ref_idx, ref_cs = oracle.cell_sort(idx, n_live, cid, n_cell)
+        else:
+            big.shuffle_per_cell(d_cs, d_idx, nl, None, dev(cid), n_cell, None,
+                                 sdm.rng(31, 0, 4))
+            u = oracle.urand(n_sd, 31, 0, 4, oracle.STREAM_SHUFFLE)
+            ref_idx, ref_cs = oracle.shuffle_per_cell(idx, n_live, cid, n_cell, u)
+        _sync()
+        assert np.array_equal(host(d_idx, np.uint32)[:n_live], ref_idx[:n_live]), routine
+        assert np.array_equal(host(d_cs, np.uint32), ref_cs), routine
+    big.close()
+
+
+@pytest.mark.parametrize("caps", [(32, -1), (0, 64), (16, 40)])
+def test_list_routines_overflow_and_global_sort_paths(sdm, caps):
+    """Tiny buckets / group capacities force the list routines through the
+    overflow and global-memory bitonic paths: results unchanged."""
+    import torch
+    for n_sd, n_cell in ((20000, 1), (12000, 300)):
+        c = sdm.Context(n_sd, n_cell, 1)
+        c.set_plan_limits(*caps)
+        cid, idx = _cells(n_sd, n_cell, 21)
+        u = oracle.urand(n_sd, 8, 1, 2, oracle.STREAM_SHUFFLE)
+        ref_idx, ref_cs = oracle.shuffle_per_cell(idx, n_sd, cid, n_cell, u)
+        d_idx, d_cs = dev(idx), zeros(n_cell + 1, torch.int32)
+        c.shuffle_per_cell(d_cs, d_idx, dev(np.array([n_sd], np.int64)), None, dev(cid),
+                           n_cell, None, sdm.rng(8, 1, 2))
+        _sync()
+        assert np.array_equal(host(d_idx, np.uint32), ref_idx), (caps, n_cell)
+        assert np.array_equal(host(d_cs, np.uint32), ref_cs), (caps, n_cell)
+        ref_idx, ref_cs = oracle.cell_sort(idx, n_sd, cid, n_cell)
+        d_idx, d_cs = dev(idx), zeros(n_cell + 1, torch.int32)
+        c.cell_sort(d_cs, d_idx, dev(np.array([n_sd], np.int64)), dev(cid), n_cell)
+        _sync()
+        assert np.array_equal(host(d_idx, np.uint32), ref_idx), (caps, n_cell)
+        assert np.array_equal(host(d_cs, np.uint32), ref_cs), (caps, n_cell)
+        c.close()
