@@ -432,6 +432,7 @@ int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch, const sdm
         SDM_HIP(hipEventCreate(&e0));
         SDM_HIP(hipEventCreate(&e1));
         double best_ms = 1e300;
+        std::vector<::sdm::PlanShape> timed;
         for (int sch = 0; sch < n_schedules(); ++sch) {
             Plan *cand = nullptr;
             try {
@@ -439,6 +440,12 @@ int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch, const sdm
             } catch (const ::sdm::HipError &) {
                 continue;  // this schedule does not fit the plan limits
             }
+            const ::sdm::PlanShape sh = ::sdm::shape_of(cand);
+            if (std::find(timed.begin(), timed.end(), sh) != timed.end()) {
+                free_plan(cand);  // the same plan as a schedule already timed
+                continue;
+            }
+            timed.push_back(sh);
             StepInputs in;
             batch_inputs(b, scratch, p, in);
             in.gamma_out = nullptr;

@@ -48,6 +48,7 @@ constexpr int GROUP_EPT_L = 8;       // plans whose buckets hold more than GROUP
 constexpr int MAXB = 32;             // buckets per group
 constexpr int MAX_TILES = 2048;      // tiles per launch
 constexpr int MAX_B = 16384;         // buckets per plan (LDS histogram)
+constexpr int MAX_B_BATCH = 1 << 18; // batched plans (a tile histograms only its runs' buckets)
 constexpr int TILE_LDS_BUDGET = 150 * 1024;
 constexpr double BUCKET_TARGET = 1024.0;
 constexpr double GROUP_TARGET = 3100.0;  // expected SDs per group of GROUP_EPT_S plans
@@ -81,6 +82,10 @@ struct TileArgs {
     const uint32_t *seg_len;
     const int32_t *seg_run;
     uint16_t *tile_off;
+    uint32_t tile_slots;   // SD slots of a tile (even, <= THREADS * EPT)
+    const int32_t *tile_lb;      // batched plans: the tile's local bucket range
+    const int32_t *tile_nb;
+    const uint32_t *tile_loff;
     RecK *rec_k;           // list modes: (key, id)
     uint64_t *rec_f;       // fused mode records (8 B, RF_* layout)
     uint32_t chunk;        // 16-B records per LDS staging pass
@@ -100,7 +105,11 @@ struct GroupArgs {
     const uint8_t *sub_bits;
     const int32_t *cell_h;
     const int32_t *cell_bucket_base;
-    const uint16_t *tile_offT;  // [B+1][n_tiles]
+    const uint16_t *tile_offT;  // [B+1][n_tiles] (dense plans)
+    const uint16_t *tile_off;   // batched plans: local tables
+    const int32_t *tile_lb;
+    const int32_t *tile_nb;
+    const uint32_t *tile_loff;
     const RecK *rec_k;
     const uint64_t *rec_f;
     const int32_t *cell_id;
@@ -358,6 +367,54 @@ __global__ __launch_bounds__(THREADS) void k_colsum(ScanArgs a)
     }
 }
 
+// Batched plans: a tile holds the SDs of a few consecutive runs, so its
+// table covers only their buckets (lb .. lb + nb - 1, plus the total).
+// Bucket b's start rank = the totals of the tiles wholly below b (an
+// exclusive scan of the tile totals) plus the local offsets of b in the
+// tiles that straddle it (bk_ta[b] .. bk_tc[b] - 1, a handful).
+struct BatchScanArgs {
+    const uint16_t *tile_off;
+    const uint32_t *tile_loff;
+    const int32_t *tile_lb;
+    const int32_t *tile_nb;
+    const int32_t *bk_ta;
+    const int32_t *bk_tc;
+    int32_t n_tiles;
+    int32_t B;
+    uint32_t *bucket_start;  // [B+1]
+};
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_colsum_batch(BatchScanArgs a)
+{
+    __shared__ uint32_t tt[MAX_TILES + 1];
+    __shared__ uint32_t red[THREADS / 64 + 1];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < a.n_tiles; t += THREADS)
+        tt[t] = a.tile_off[a.tile_loff[t] + (uint32_t)a.tile_nb[t]];
+    __syncthreads();
+    lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(tt, a.n_tiles, red);
+    for (int b = blockIdx.x * THREADS + tid; b <= a.B; b += gridDim.x * THREADS) {
+        const int ta = a.bk_ta[b], tc = a.bk_tc[b];
+        uint32_t sum = tt[ta];
+        for (int t = ta; t < tc; ++t)
+            sum += a.tile_off[a.tile_loff[t] + (uint32_t)(b - a.tile_lb[t])];
+        a.bucket_start[b] = sum;
+    }
+}
+
+// Exclusive offset of bucket b in tile t: the dense table, or a batched
+// plan's local one (0 below the tile's buckets, its total above them).
+template <class Args>
+__device__ __forceinline__ uint32_t tile_bucket_off(const Args &a, int t, int b)
+{
+    if (!a.tile_lb)
+        return a.tile_offT[(int64_t)b * a.n_tiles + t];
+    const int lb = a.tile_lb[t], nb = a.tile_nb[t];
+    const int i = b <= lb ? -1 : min(b - lb, nb);
+    return i < 0 ? 0u : (uint32_t)a.tile_off[a.tile_loff[t] + (uint32_t)i];
+}
+
 // ---------------------------------------------------------------- k_tile
 template <int THREADS, int EPT, bool LIST>
 __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
@@ -366,11 +423,15 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t scan_scratch[THREADS / 64 + 1];
     const int B = a.B;
+    // this tile's buckets: all B, or (batched plans) those of its runs,
+    // lb .. lb + NB - 1; hist[NB] receives the total
+    const int lb = a.tile_lb ? a.tile_lb[blockIdx.x] : 0;
+    const int NB = a.tile_lb ? a.tile_nb[blockIdx.x] : B;
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
-    const int hist_bytes = ((B + 1) * 4 + 15) & ~15;
+    const int hist_bytes = ((NB + 1) * 4 + 15) & ~15;
     uint64_t *stage = reinterpret_cast<uint64_t *>(smem + hist_bytes);
     const int tid = threadIdx.x;
-    for (int i = tid; i <= B; i += THREADS)
+    for (int i = tid; i <= NB; i += THREADS)
         hist[i] = 0;
     if (a.start_zero)
         for (int i = blockIdx.x * THREADS + tid; i <= B; i += gridDim.x * THREADS)
@@ -378,7 +439,10 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
 
     const uint32_t step = step_of(a.step, a.step_dev);
     const int64_t n_items = LIST ? *a.n_live_in : a.n_sd;
-    const int64_t pair0 = (int64_t)blockIdx.x * (T / 2);
+    // slots [2 pair0, lim) of the launch's n_items belong to this tile
+    const uint32_t TS = a.tile_slots;
+    const int64_t pair0 = (int64_t)blockIdx.x * (TS / 2);
+    const int64_t lim = min(n_items, 2 * pair0 + (int64_t)TS);
 
     // batched runs (fused mode): the runs this tile's slots fall in, with
     // their offset, length, Philox run, key bits and first bucket, in LDS
@@ -393,7 +457,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         if (tid == 0) {
             const int64_t last = n_items > 0 ? n_items - 1 : 0;
             const uint32_t s_lo = (uint32_t)min<int64_t>(2 * pair0, last);
-            const uint32_t s_hi = (uint32_t)min<int64_t>(2 * pair0 + T - 1, last);
+            const uint32_t s_hi = (uint32_t)min<int64_t>(2 * pair0 + TS - 1, last);
             const int f = find_seg(a.seg_off, a.n_cell, s_lo);
             const int l = find_seg(a.seg_off, a.n_cell, s_hi);
             st_first = f;
@@ -430,8 +494,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     // every slot pair's loads (xi, v, cell ids) are issued before any of
     // them is used, from clamped addresses, so that they are all in flight
     // together; the odd last slot of the launch is read on its own below.
-    // With 16 slots per thread (bandwidth bound) each pair is loaded where
-    // it is used, which overlaps the loads with the key arithmetic.
+    // With 16 slots per thread each pair is loaded where it is used (all
+    // loaded up front measured slower: the tile kernel is issue-bound there).
     constexpr bool PRELOAD = !LIST && EPT <= 8;
     constexpr bool EARLY_CID = PRELOAD;
     uint32_t cid[EARLY_CID ? EPT : 1];
@@ -439,7 +503,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
 #pragma unroll
         for (int k = 0; k < EPT / 2; ++k) {
             const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
-            const int64_t ia = i0 + 1 < n_items ? i0 : 0;
+            const int64_t ia = i0 + 1 < lim ? i0 : 0;
             const ulonglong2 xx = *reinterpret_cast<const ulonglong2 *>(a.xi + ia);
             xv[2 * k] = xx.x;
             xv[2 * k + 1] = xx.y;
@@ -467,14 +531,14 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             s[0] = (uint32_t)i0;
             s[1] = (uint32_t)(i0 + 1);
             double v[2] = {0.0, 0.0};
-            if (i0 + 1 < n_items && PRELOAD) {
+            if (i0 + 1 < lim && PRELOAD) {
                 x[0] = xv[2 * k];
                 x[1] = xv[2 * k + 1];
                 if (EARLY_V) {
                     v[0] = vv[2 * k];
                     v[1] = vv[2 * k + 1];
                 }
-            } else if (i0 + 1 < n_items) {
+            } else if (i0 + 1 < lim) {
                 const ulonglong2 xx = *reinterpret_cast<const ulonglong2 *>(a.xi + i0);
                 x[0] = xx.x;
                 x[1] = xx.y;
@@ -483,7 +547,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                     v[0] = v2.x;
                     v[1] = v2.y;
                 }
-            } else if (i0 < n_items) {
+            } else if (i0 < lim) {
                 x[0] = a.xi[i0];
                 if (EARLY_V)
                     v[0] = a.v[i0];
@@ -495,8 +559,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             live[0] = x[0] > 0;
             live[1] = x[1] > 0;
         } else {
-            live[0] = i0 < n_items;
-            live[1] = i0 + 1 < n_items;
+            live[0] = i0 < lim;
+            live[1] = i0 + 1 < lim;
             s[0] = live[0] ? a.idx_in[i0] : 0;
             s[1] = live[1] ? a.idx_in[i0 + 1] : 0;
         }
@@ -523,7 +587,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             for (int e = 0; e < 2; ++e)
                 if (s[e] - a.seg_off[cell[e]] >= a.seg_len[cell[e]])
                     live[e] = false;
-        } else if (EARLY_CID && i0 + 1 < n_items) {
+        } else if (EARLY_CID && i0 + 1 < lim) {
 #pragma unroll
             for (int e = 0; e < 2; ++e)
                 cell[e] = (a.cell_id && live[e]) ? (int32_t)cid[2 * k + e] : 0;
@@ -584,8 +648,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
                 const uint32_t bb =
                     (uint32_t)(ti >= 0 ? st_bb[ti] : a.cell_bucket_base[cell[e]]);
                 const uint32_t b = bb + (h ? (uint32_t)(kk[e] >> (53 - h)) : 0u);
-                const uint32_t r = atomicAdd(&hist[b], 1u);
-                bk[j] = b | (r << 16);
+                const uint32_t r = atomicAdd(&hist[b - (uint32_t)lb], 1u);
+                bk[j] = (b - (uint32_t)lb) | (r << 16);
                 if (!LIST)  // the 24 key bits below the bucket's, and the bucket mod 32
                     k32[j] = ((uint32_t)(kk[e] >> (29 - h)) & 0xFFFFFFu) | ((b & 31u) << 24);
             }
@@ -594,8 +658,8 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     __syncthreads();
     // exclusive bucket offsets of this tile
     {
-        const int chunk = (B + THREADS - 1) / THREADS;
-        const int lo = min(B, tid * chunk), hi = min(B, lo + chunk);
+        const int chunk = (NB + THREADS - 1) / THREADS;
+        const int lo = min(NB, tid * chunk), hi = min(NB, lo + chunk);
         uint32_t sum = 0;
         for (int b = lo; b < hi; ++b)
             sum += hist[b];
@@ -607,16 +671,17 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             run += c;
         }
         if (tid == 0) {
-            hist[B] = total;
+            hist[NB] = total;
             if (total)
                 atomicAdd(&a.n_acc[0], total);
         }
         __syncthreads();
     }
-    uint16_t *toff = a.tile_off + (int64_t)blockIdx.x * (B + 1);
-    for (int b = tid; b <= B; b += THREADS)
+    uint16_t *toff = a.tile_off + (a.tile_lb ? (int64_t)a.tile_loff[blockIdx.x]
+                                             : (int64_t)blockIdx.x * (B + 1));
+    for (int b = tid; b <= NB; b += THREADS)
         toff[b] = (uint16_t)hist[b];
-    const uint32_t total = hist[B];
+    const uint32_t total = hist[NB];
     uint32_t pos[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -626,7 +691,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     // staged, coalesced write-out of the tile's records in bucket order.
     // Fused mode: one 24-B record (id, 24 key bits and the bucket, xi, v);
     // list modes: (key, id).  Passes of a.chunk 16-B records.
-    const int64_t rbase = (int64_t)blockIdx.x * T;
+    const int64_t rbase = (int64_t)blockIdx.x * TS;
     const uint32_t CH = a.chunk;
     if (LIST) {  // the list modes (the fused step always runs LIST = false)
         RecK *stk = reinterpret_cast<RecK *>(stage);
@@ -660,7 +725,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
             const int64_t i0 = 2 * (pair0 + (int64_t)k * THREADS + tid);
             double v0 = 0.0, v1 = 0.0;
             if (pos[2 * k] != 0xFFFFFFFFu || pos[2 * k + 1] != 0xFFFFFFFFu) {
-                if (i0 + 1 < n_items) {
+                if (i0 + 1 < lim) {
                     const double2 v2 = *reinterpret_cast<const double2 *>(a.v + i0);
                     v0 = v2.x;
                     v1 = v2.y;
@@ -1081,8 +1146,8 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
 
     // 1. this group's run in each of those tiles; bucket and cell tables
     for (int t = tid; t < ntl; t += THREADS) {
-        const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
-        const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
+        const uint32_t lo = tile_bucket_off(a, t_first + t, b0);
+        const uint32_t hi = tile_bucket_off(a, t_first + t, b1);
         run_base[t] = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
         run_pre[t] = hi - lo;
     }
@@ -1166,9 +1231,15 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
         uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);  // tile of each gathered slot
         const uint32_t nsub = t_subbase[nb];
-        for (int t = tid; t < ntl; t += THREADS)
-            for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
-                tmap[li] = (uint16_t)t;
+        if (ntl <= 8) {  // a few long runs (batches): every thread on each
+            for (int t = 0; t < ntl; ++t)
+                for (uint32_t li = run_pre[t] + tid; li < run_pre[t + 1]; li += THREADS)
+                    tmap[li] = (uint16_t)t;
+        } else {         // many short runs: a thread per run
+            for (int t = tid; t < ntl; t += THREADS)
+                for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
+                    tmap[li] = (uint16_t)t;
+        }
         __syncthreads();
         // fused mode: the record carries the 24 key bits below its bucket's
         // (bits 28 - h .. 52 - h) and the bucket's low 8 bits; they fix the
@@ -1674,14 +1745,44 @@ static uint32_t tile_chunk_for(int B, int tile)
     return (int)(ch * sizeof(RecK)) <= room ? ch : 0;
 }
 
+// Tiles of a launch: the largest power-of-two tile (1024 threads times 4,
+// 8 or 16 slots, at most ept_max) that still gives every CU one, and then,
+// when a launch needs more than one round of TILE_FILL tiles, a whole
+// number of rounds of equal (even) slot counts, so that the last round is
+// not a short tail.
+static void choose_tiles(Plan *p, int64_t n_items, int ept_max)
+{
+    int ept = ept_max;
+    while (ept > 4 &&
+           (n_items + (int64_t)TILE_THREADS * ept - 1) / ((int64_t)TILE_THREADS * ept) < TILE_FILL)
+        ept /= 2;
+    const int64_t T = (int64_t)TILE_THREADS * ept;
+    int64_t nt = std::max<int64_t>(1, (n_items + T - 1) / T);
+    int64_t tile = T;
+    if (nt > TILE_FILL) {
+        nt = (nt + TILE_FILL - 1) / TILE_FILL * TILE_FILL;
+        tile = (n_items + nt - 1) / nt;
+        tile += tile & 1;
+        nt = std::max<int64_t>(1, (n_items + tile - 1) / tile);
+    }
+    if (nt > MAX_TILES)
+        throw HipError{hipErrorInvalidValue, "too many SD slots for one plan"};
+    p->tile_ept = ept;
+    p->tile = (int32_t)tile;
+    p->n_tiles = (int32_t)nt;
+}
+
 static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                         const std::vector<double> &expected, double bucket_target,
-                        double group_target)
+                        double group_target, const std::vector<uint32_t> *seg_off = nullptr,
+                        int tile_ept_max = TILE_EPT_MAX)
 {
     Plan *p = new Plan();
     try {
         (void)ctx;
         const int32_t C = (int32_t)expected.size();
+        const bool batched = seg_off != nullptr;
+        const int64_t max_b = batched ? MAX_B_BATCH : MAX_B;
         // the bucket table must fit the tile kernel's LDS histogram: coarser
         // buckets for plans with many SDs
         double target = bucket_target;
@@ -1694,7 +1795,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                     ++h;
                 nbk += (int64_t)1 << h;
             }
-            if (nbk <= MAX_B || target >= 1e12)
+            if (nbk <= max_b || target >= 1e12)
                 break;
             target *= 2.0;
         }
@@ -1743,7 +1844,7 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
                 sub_bits.push_back((uint8_t)u);
                 bucket_exp.push_back(e);
                 ++B;
-                if (B > MAX_B)
+                if (B > max_b)
                     throw HipError{hipErrorInvalidValue, "too many buckets for one plan"};
             }
         }
@@ -1770,20 +1871,58 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             }
             group_first.push_back(B);
         }
-        // the largest tile that still gives every CU a tile (longer runs for
-        // the groups), at least 4 slots per thread
-        int ept = TILE_EPT_MAX;
-        while (ept > 4 &&
-               (n_items + (int64_t)TILE_THREADS * ept - 1) / ((int64_t)TILE_THREADS * ept) <
-                   TILE_FILL)
-            ept /= 2;
-        p->tile = TILE_THREADS * ept;
-        p->chunk = tile_chunk_for(B, p->tile);
+        choose_tiles(p, n_items, tile_ept_max);
+        p->B = B;
+        p->lhist = B;
+        std::vector<int32_t> t_lb, t_nb, bk_ta, bk_tc;
+        std::vector<uint32_t> t_loff;
+        int64_t n_off = (int64_t)p->n_tiles * (B + 1);
+        if (batched) {
+            // each tile's runs (first and last run meeting its slots) and
+            // their bucket range; the local tables packed one after another
+            const std::vector<uint32_t> &so = *seg_off;
+            auto run_of = [&](uint32_t slot) {  // largest r with so[r] <= slot
+                return (int32_t)(std::upper_bound(so.begin(), so.begin() + C, slot) - so.begin()) - 1;
+            };
+            t_lb.resize(p->n_tiles);
+            t_nb.resize(p->n_tiles);
+            t_loff.resize(p->n_tiles);
+            int64_t acc = 0;
+            int lmax = 0;
+            for (int32_t t = 0; t < p->n_tiles; ++t) {
+                const int64_t s0 = (int64_t)t * p->tile;
+                const int64_t s1 = std::min<int64_t>(s0 + p->tile, n_items) - 1;
+                const int32_t f = std::max(0, run_of((uint32_t)s0));
+                const int32_t l = std::max(f, run_of((uint32_t)s1));
+                t_lb[t] = cell_bb[f];
+                t_nb[t] = cell_bb[l + 1] - cell_bb[f];
+                t_loff[t] = (uint32_t)acc;
+                acc += t_nb[t] + 1;
+                lmax = std::max(lmax, t_nb[t]);
+            }
+            if (lmax >= (int)NO_BUCKET || acc >= ((int64_t)1 << 32))
+                throw HipError{hipErrorInvalidValue, "a tile meets too many buckets"};
+            n_off = acc;
+            p->lhist = lmax;
+            // bucket b: tiles wholly below it (their last bucket < b) and
+            // tiles beginning below it; both nondecreasing in t
+            bk_ta.resize(B + 1);
+            bk_tc.resize(B + 1);
+            int32_t ta = 0, tc = 0;
+            for (int32_t b = 0; b <= B; ++b) {
+                while (ta < p->n_tiles && t_lb[ta] + t_nb[ta] <= b)
+                    ++ta;
+                while (tc < p->n_tiles && t_lb[tc] < b)
+                    ++tc;
+                bk_ta[b] = ta;
+                bk_tc[b] = tc;
+            }
+        }
+        p->chunk = tile_chunk_for(p->lhist, p->tile);
         if (p->chunk == 0)
             throw HipError{hipErrorInvalidValue, "bucket table exceeds the tile LDS budget"};
-        p->n_tiles = (int32_t)std::max<int64_t>(1, (n_items + p->tile - 1) / p->tile);
-        if (p->n_tiles > MAX_TILES)
-            throw HipError{hipErrorInvalidValue, "too many SD slots for one plan"};
+        p->bucket_target = target;
+        p->group_target = group_target;
         p->B = B;
         p->G = (int32_t)group_first.size() - 1;
         p->cell_h = upload(p, cell_h);
@@ -1793,8 +1932,16 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
         p->group_first = upload(p, group_first);
         const bool fused = mode == MODE_FUSED;
         const size_t R = (size_t)p->n_tiles * p->tile;
-        p->tile_off = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
-        p->tile_offT = (uint16_t *)dalloc(p, 2ull * p->n_tiles * (B + 1));
+        p->tile_off = (uint16_t *)dalloc(p, 2ull * (size_t)n_off);
+        if (batched) {
+            p->tile_lb = upload(p, t_lb);
+            p->tile_nb = upload(p, t_nb);
+            p->tile_loff = upload(p, t_loff);
+            p->bk_ta = upload(p, bk_ta);
+            p->bk_tc = upload(p, bk_tc);
+        } else {
+            p->tile_offT = (uint16_t *)dalloc(p, 2ull * (size_t)n_off);
+        }
         if (fused) {
             p->rec_f = (uint64_t *)dalloc(p, sizeof(uint64_t) * R);
         } else {
@@ -1843,12 +1990,21 @@ Plan *get_plan(sdm_ctx *ctx, int mode, int64_t n_items, int32_t n_cell,
 }
 
 // Schedules the batch autotuner chooses from: (expected SDs per key bucket,
-// expected SDs per group).  Results never depend on the choice.
-static const double kSchedules[][2] = {
-    {1024.0, 3100.0}, {512.0, 3100.0}, {2048.0, 3100.0},
-    {1024.0, 2400.0}, {512.0, 2400.0}, {512.0, 1600.0},
+// expected SDs per group, largest tile-kernel slots per thread).  Results
+// never depend on the choice; schedules that build the same plan for a
+// batch are timed once.
+static const double kSchedules[][3] = {
+    {1024.0, 3100.0, 16}, {512.0, 3100.0, 16},  {2048.0, 3100.0, 16}, {256.0, 3100.0, 16},
+    {1024.0, 2400.0, 16}, {512.0, 2400.0, 16},  {512.0, 1600.0, 16},  {4096.0, 3100.0, 16},
+    {512.0, 3100.0, 8},   {1024.0, 3100.0, 8},  {512.0, 2400.0, 8},   {256.0, 2400.0, 16},
 };
 int n_schedules() { return (int)(sizeof(kSchedules) / sizeof(kSchedules[0])); }
+
+PlanShape shape_of(const Plan *p)
+{
+    return PlanShape{p->B,        p->G,    p->tile,          p->n_tiles,      p->tile_ept,
+                     p->gept,     p->chunk, p->bucket_target, p->group_target};
+}
 
 Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64_t n_items,
                        int schedule)
@@ -1857,24 +2013,27 @@ Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64
     for (size_t i = 0; i < segs.size(); ++i)
         exp[i] = (double)segs[i].n_sd;
     double bt = kSchedules[schedule][0], gt = kSchedules[schedule][1];
+    const int ept = (int)kSchedules[schedule][2];
     if (ctx->dbg_bucket_target > 0)
         bt = (double)ctx->dbg_bucket_target;
-    Plan *p = build_plan(ctx, MODE_FUSED, n_items, exp, bt, gt);
+    const int C = (int)segs.size();
+    std::vector<uint32_t> off(C + 1), len(C);
+    for (int c = 0; c < C; ++c) {
+        off[c] = (uint32_t)segs[c].offset;
+        len[c] = (uint32_t)segs[c].n_sd;
+    }
+    off[C] = (uint32_t)n_items;
+    Plan *p = build_plan(ctx, MODE_FUSED, n_items, exp, bt, gt, &off, ept);
     try {
-        const int C = (int)segs.size();
-        std::vector<uint32_t> off(C + 1), len(C);
         std::vector<int32_t> run(C), kidx(C);
         std::vector<double> dv(C);
         std::vector<KernelDesc> kernels(C);
         for (int c = 0; c < C; ++c) {
-            off[c] = (uint32_t)segs[c].offset;
-            len[c] = (uint32_t)segs[c].n_sd;
             run[c] = (int32_t)segs[c].run;
             dv[c] = segs[c].dv;
             kidx[c] = c;
             kernels[c] = kernel_desc(segs[c].kernel);
         }
-        off[C] = (uint32_t)n_items;
         p->seg_off = upload(p, off);
         p->seg_len = upload(p, len);
         p->seg_run = upload(p, run);
@@ -1946,20 +2105,38 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.seg_len = p->seg_len;
     ta.seg_run = p->seg_run;
     ta.tile_off = p->tile_off;
+    ta.tile_slots = (uint32_t)p->tile;
+    ta.tile_lb = p->tile_lb;
+    ta.tile_nb = p->tile_nb;
+    ta.tile_loff = p->tile_loff;
     ta.rec_k = p->rec_k;
     ta.rec_f = p->rec_f;
     ta.chunk = p->chunk;
-    ta.start_zero = p->n_tiles > 64 ? p->bucket_start : nullptr;
+    ta.start_zero = (p->n_tiles > 64 && !p->tile_lb) ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
-    const size_t lds = (size_t)tile_hist_bytes(p->B) + (size_t)p->chunk * sizeof(RecK);
+    const size_t lds = (size_t)tile_hist_bytes(p->lhist) + (size_t)p->chunk * sizeof(RecK);
     mark(0);
     if (list)
-        launch_tile_ept<true>(p->tile / TILE_THREADS, p->n_tiles, lds, stream, ta);
+        launch_tile_ept<true>(p->tile_ept, p->n_tiles, lds, stream, ta);
     else
-        launch_tile_ept<false>(p->tile / TILE_THREADS, p->n_tiles, lds, stream, ta);
+        launch_tile_ept<false>(p->tile_ept, p->n_tiles, lds, stream, ta);
     SDM_HIP(hipGetLastError());
-    {
+    if (p->tile_lb) {
+        BatchScanArgs sa{};
+        sa.tile_off = p->tile_off;
+        sa.tile_loff = p->tile_loff;
+        sa.tile_lb = p->tile_lb;
+        sa.tile_nb = p->tile_nb;
+        sa.bk_ta = p->bk_ta;
+        sa.bk_tc = p->bk_tc;
+        sa.n_tiles = p->n_tiles;
+        sa.B = p->B;
+        sa.bucket_start = p->bucket_start;
+        hipLaunchKernelGGL((k_colsum_batch<256>), dim3((p->B + 1 + 255) / 256), dim3(256), 0,
+                           stream, sa);
+        SDM_HIP(hipGetLastError());
+    } else {
         ScanArgs sa{};
         sa.tile_off = p->tile_off;
         sa.tile_offT = p->tile_offT;
@@ -1983,6 +2160,10 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.cell_h = p->cell_h;
     ga.cell_bucket_base = p->cell_bucket_base;
     ga.tile_offT = p->tile_offT;
+    ga.tile_off = p->tile_off;
+    ga.tile_lb = p->tile_lb;
+    ga.tile_nb = p->tile_nb;
+    ga.tile_loff = p->tile_loff;
     ga.rec_k = p->rec_k;
     ga.rec_f = p->rec_f;
     ga.cell_id = in.cell_id;

@@ -100,8 +100,11 @@ struct Plan {
     int64_t n_items = 0;  // SD slots (fused) or index capacity (list modes)
     int32_t n_cell = 0;
     int32_t B = 0, G = 0;
-    int32_t tile = 0;     // SD slots per scatter tile
+    int32_t tile = 0;     // SD slots per scatter tile (even, <= 1024 tile_ept)
+    int32_t tile_ept = 0; // slots per tile-kernel thread (4, 8 or 16)
     int32_t n_tiles = 0;
+    int32_t lhist = 0;    // tile-kernel histogram entries (B, or the largest local range)
+    double bucket_target = 0, group_target = 0;  // effective plan targets
     // device tables
     int32_t *cell_h = nullptr;            // [C]
     int32_t *cell_bucket_base = nullptr;  // [C+1]
@@ -115,9 +118,19 @@ struct Plan {
     int32_t *seg_kernel = nullptr;        // [C] index into kernel table
     double *seg_dv = nullptr;             // [C]
     KernelDesc *kernels = nullptr;        // [n_kernels]
+    // batched plans: tile t holds SDs of runs whose buckets are
+    // [tile_lb[t], tile_lb[t] + tile_nb[t]); its exclusive offsets of those
+    // buckets and its total (tile_nb[t] + 1 entries) sit at tile_loff[t] in
+    // tile_off.  bk_ta[b] tiles lie wholly below bucket b, bk_tc[b] begin
+    // below it.  Null for the other plans (dense tables).
+    int32_t *tile_lb = nullptr;           // [n_tiles]
+    int32_t *tile_nb = nullptr;           // [n_tiles]
+    uint32_t *tile_loff = nullptr;        // [n_tiles]
+    int32_t *bk_ta = nullptr;             // [B+1]
+    int32_t *bk_tc = nullptr;             // [B+1]
     // workspace
-    uint16_t *tile_off = nullptr;         // [n_tiles][B+1]
-    uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy)
+    uint16_t *tile_off = nullptr;         // [n_tiles][B+1], or the batched plans' local tables
+    uint16_t *tile_offT = nullptr;        // [B+1][n_tiles] (bucket-major copy; dense plans)
     // records in tile-local bucket order, [n_tiles * tile]
     RecK *rec_k = nullptr;                // list modes: (key, id)
     uint64_t *rec_f = nullptr;            // fused mode records (8 B)
@@ -223,6 +236,19 @@ void engine_run(sdm_ctx *ctx, Plan *plan, const StepInputs &in, hipStream_t stre
 
 // batched ensembles (sdm_engine.hip)
 int n_schedules();
+// What a plan's launches depend on: schedules giving equal shapes are the same.
+struct PlanShape {
+    int32_t B, G, tile, n_tiles, tile_ept, gept;
+    uint32_t chunk;
+    double bucket_target, group_target;
+    bool operator==(const PlanShape &o) const
+    {
+        return B == o.B && G == o.G && tile == o.tile && n_tiles == o.n_tiles &&
+               tile_ept == o.tile_ept && gept == o.gept && chunk == o.chunk &&
+               bucket_target == o.bucket_target && group_target == o.group_target;
+    }
+};
+PlanShape shape_of(const Plan *p);
 Plan *build_batch_plan(sdm_ctx *ctx, const std::vector<sdm_segment> &segs, int64_t n_items,
                        int schedule);
 

@@ -187,6 +187,17 @@ def test_full_size_box_2_22(sdm):
     ctx.close()
 
 
+def test_box_tiles_of_a_whole_number_of_rounds(sdm):
+    """2^22 + 4098 SDs need 257 tiles of 16384 slots; the plan takes 512
+    tiles of 8200 instead (two full rounds on the CUs, no one-tile tail):
+    one step against the oracle, element by element."""
+    n_sd = (1 << 22) + 4098
+    w = workloads.box(n_sd, seed=8)
+    ctx = sdm.Context(n_sd, 1, 1)
+    _run_pair(sdm, ctx, w, 1, seed=8, gamma=True)
+    ctx.close()
+
+
 def test_graph_replay_matches_eager(sdm):
     import torch
     n_sd = 30000
