@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SDM_ABI_VERSION 2
+#define SDM_ABI_VERSION 3
 
 typedef enum {
     SDM_OK = 0,
@@ -412,7 +412,7 @@ int sdm_reassign(sdm_ctx *ctx, int32_t *cell_id, int64_t n_sd, int32_t n_cell,
  * order W1, b1, W2, b2, W3, b3, W4, b4, each W row-major [out][in]. */
 #define SDM_MLP_N_PARAMS 34179
 #define SDM_MLP_PACKED_BYTES 151552   /* bf16 weights in the kernels' order */
-#define SDM_MLP_CACHE_FLOATS_PER_ROW 384
+#define SDM_MLP_CACHE_FLOATS_PER_ROW 576
 
 typedef struct {
     float *params;           /* device float[SDM_MLP_N_PARAMS]: fp32 masters */
@@ -438,7 +438,8 @@ int sdm_mlp_pack(sdm_ctx *ctx, const sdm_mlp *w, hipStream_t stream);
 
 /* y[B][3] = network(x[B][5]) (device float, row-major).  cache: NULL for
  * inference, or device float[ceil(B/16)*16 * SDM_MLP_CACHE_FLOATS_PER_ROW]
- * receiving the hidden pre-activations for sdm_mlp_backward (layout private
+ * receiving, for sdm_mlp_backward, the derivative GELU'(z) of every hidden
+ * unit and the bf16 activations the forward pass used (layout private
  * to the library).  B = 0 is a no-op. */
 int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_t B,
                     const sdm_mlp *w, hipStream_t stream);

@@ -127,7 +127,7 @@ SIGNATURES = {
 
 MLP_N_PARAMS = 34179
 MLP_PACKED_BYTES = 151552
-MLP_CACHE_FLOATS_PER_ROW = 384
+MLP_CACHE_FLOATS_PER_ROW = 576
 
 _lib = None
 

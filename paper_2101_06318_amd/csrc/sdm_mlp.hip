@@ -19,10 +19,13 @@
 // share a tile's hidden layers (k_mlp_forward_split), which spreads the
 // GELU work over more waves.
 //
-// Weight gradients dW = dZ^T A sum over samples, a different operand
-// layout; there the workgroup stages dZ^T and A^T of its 64 samples in LDS
-// and each wave takes a share of the output tiles.  Per-workgroup partial
-// sums are reduced in a fixed order by a second kernel (deterministic).
+// Training: the forward pass also keeps, per hidden unit, GELU'(z) and the
+// bf16 activation it fed to the next layer, so the backward pass is matmuls
+// and products only.  Weight gradients dW = dZ^T A sum over samples, a
+// different operand layout; there the workgroup stages dZ^T and A^T of its
+// 64 samples in LDS and each wave takes a share of the output tiles.
+// Per-workgroup partial sums are reduced in a fixed order by a second kernel
+// (deterministic).
 #include <math.h>
 
 #include <cmath>
@@ -47,7 +50,13 @@ static_assert(NPARAM == SDM_MLP_N_PARAMS, "parameter count");
 constexpr int FR_F1 = 0, FR_F2 = 8, FR_F3 = 40, FR_F4 = 72, FR_B4 = 76, FR_B3 = 84,
               FR_B2 = 116, FR_N = 148, FWD_FRAGS = 76;
 static_assert(FR_N * 1024 == SDM_MLP_PACKED_BYTES, "packed size");
-static_assert(3 * 8 * 64 * 4 == 16 * SDM_MLP_CACHE_FLOATS_PER_ROW, "cache tile size");
+// Training cache of a 16-sample tile: GELU'(z) of the three hidden layers
+// (fp32, [layer][t][lane] f32x4, the MFMA output layout) and the bf16
+// activations GELU(z) the forward pass fed to the next layer ([layer][t][lane]
+// two words), so that the backward pass evaluates no transcendental.
+constexpr int CACHE_GG = 3 * 8 * 64 * 4;       // floats
+constexpr int CACHE_TILE = CACHE_GG + 3 * 8 * 64 * 2;
+static_assert(CACHE_TILE == 16 * SDM_MLP_CACHE_FLOATS_PER_ROW, "cache tile size");
 
 constexpr int BWD_CHUNK = 64;      // samples per backward workgroup pass
 constexpr int BWD_ROW = 72;        // LDS row stride (bf16): 64 samples + 8 pad
@@ -82,10 +91,53 @@ __device__ inline float gelu(float z)
     return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
 }
 
-__device__ inline float gelu_grad(float z)
+// gelu(z) (the same expression, so the same bits) and its derivative
+// Phi(z) + z phi(z), with one erf.
+__device__ inline void gelu_both(float z, float &h, float &gg)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * (expf(-0.5f * z * z) * 0.39894228040143268f);
+    const float e = erff(z * 0.70710678118654752f);
+    h = 0.5f * z * (1.0f + e);
+    gg = 0.5f * (1.0f + e) + z * (expf(-0.5f * z * z) * 0.39894228040143268f);
+}
+
+__device__ inline float *cache_gg(float *cache, int64_t tile, int layer, int t, int lane)
+{
+    return cache + tile * CACHE_TILE + ((layer * 8 + t) * 64 + lane) * 4;
+}
+
+__device__ inline uint32_t *cache_h(float *cache, int64_t tile, int layer, int t, int lane)
+{
+    return reinterpret_cast<uint32_t *>(cache + tile * CACHE_TILE + CACHE_GG +
+                                        ((layer * 8 + t) * 64 + lane) * 2);
+}
+
+// Epilogue of one output tile (4 neurons of a lane): the bf16 activations as
+// two words, and in training the cache entries.
+template <bool TRAIN>
+__device__ inline void gelu_tile(const f32x4 &z, uint32_t &w0, uint32_t &w1,
+                                 float *__restrict__ cache, int64_t tile, bool tv, int layer,
+                                 int t, int lane)
+{
+    float h[4];
+    if (TRAIN) {
+        float g4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            gelu_both(z[e], h[e], g4[e]);
+        const f32x4 gg{g4[0], g4[1], g4[2], g4[3]};
+        w0 = pack2(h[0], h[1]);
+        w1 = pack2(h[2], h[3]);
+        if (tv) {
+            *(f32x4 *)cache_gg(cache, tile, layer, t, lane) = gg;
+            *(uint2 *)cache_h(cache, tile, layer, t, lane) = make_uint2(w0, w1);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            h[e] = gelu(z[e]);
+        w0 = pack2(h[0], h[1]);
+        w1 = pack2(h[2], h[3]);
+    }
 }
 
 __device__ inline int perm32(int p)
@@ -141,22 +193,19 @@ __device__ inline void hidden_epilogue(const f32x4 (&acc)[S], int t, int layer,
     const int g = lane >> 4;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        float h[4];
         f32x4 z;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 4; ++e)
             z[e] = acc[j][e] + sb[layer * NH + 16 * t + 4 * g + e];
-            h[e] = gelu(z[e]);
-        }
-        if (TRAIN && tile0 + j < n_tiles)
-            *(f32x4 *)(cache + (((tile0 + j) * 3 + layer) * 8 + t) * 256 + lane * 4) = z;
+        uint32_t w0, w1;
+        gelu_tile<TRAIN>(z, w0, w1, cache, tile0 + j, tile0 + j < n_tiles, layer, t, lane);
         const int q = t >> 1;
         if (t & 1) {
-            out[j][q][2] = pack2(h[0], h[1]);
-            out[j][q][3] = pack2(h[2], h[3]);
+            out[j][q][2] = w0;
+            out[j][q][3] = w1;
         } else {
-            out[j][q][0] = pack2(h[0], h[1]);
-            out[j][q][1] = pack2(h[2], h[3]);
+            out[j][q][0] = w0;
+            out[j][q][1] = w1;
         }
     }
 }
@@ -300,20 +349,15 @@ __device__ inline u32x4 split_epilogue(const f32x4 &a0, const f32x4 &a1, int t0,
                                        float *__restrict__ cache, int64_t tile, bool tv, int lane)
 {
     f32x4 z0, z1;
-    float h0[4], h1[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         z0[e] = a0[e] + sb[layer * NH + 16 * t0 + 4 * g + e];
         z1[e] = a1[e] + sb[layer * NH + 16 * (t0 + 1) + 4 * g + e];
-        h0[e] = gelu(z0[e]);
-        h1[e] = gelu(z1[e]);
     }
-    if (TRAIN && tv) {
-        *(f32x4 *)(cache + (((tile * 3 + layer) * 8 + t0) * 256 + lane * 4)) = z0;
-        *(f32x4 *)(cache + (((tile * 3 + layer) * 8 + t0 + 1) * 256 + lane * 4)) = z1;
-    }
-    return u32x4{pack2(h0[0], h0[1]), pack2(h0[2], h0[3]), pack2(h1[0], h1[1]),
-                 pack2(h1[2], h1[3])};
+    uint32_t w[4];
+    gelu_tile<TRAIN>(z0, w[0], w[1], cache, tile, tv, layer, t0, lane);
+    gelu_tile<TRAIN>(z1, w[2], w[3], cache, tile, tv, layer, t0 + 1, lane);
+    return u32x4{w[0], w[1], w[2], w[3]};
 }
 
 template <bool TRAIN>
@@ -459,13 +503,31 @@ __device__ inline void stage_t(uint16_t *buf, const f32x4 (&v)[8], int col, int 
             buf[(16 * t + 4 * g + e) * BWD_ROW + col] = (uint16_t)bf16_bits(v[t][e]);
 }
 
-__device__ inline void load_z(f32x4 (&z)[8], const float *__restrict__ cache, int64_t tile,
-                              bool valid, int layer, int lane)
+// Same, from the cached bf16 words (lane (r, g) holding the pair words of
+// features 16t + 4g .. 16t + 4g + 3 of its sample).
+__device__ inline void stage_tb(uint16_t *buf, const uint2 (&hw)[8], int col, int g)
 {
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-        z[t] = valid ? *(const f32x4 *)(cache + ((tile * 3 + layer) * 8 + t) * 256 + lane * 4)
-                     : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 8; ++t) {
+        uint16_t *p = buf + (16 * t + 4 * g) * BWD_ROW + col;
+        p[0] = (uint16_t)(hw[t].x & 0xFFFFu);
+        p[BWD_ROW] = (uint16_t)(hw[t].x >> 16);
+        p[2 * BWD_ROW] = (uint16_t)(hw[t].y & 0xFFFFu);
+        p[3 * BWD_ROW] = (uint16_t)(hw[t].y >> 16);
+    }
+}
+
+// GELU'(z) and the bf16 activations of one hidden layer of a tile.
+__device__ inline void load_cache(f32x4 (&gg)[8], uint2 (&hw)[8], const float *__restrict__ cache,
+                                  int64_t tile, bool valid, int layer, int lane)
+{
+    float *c = const_cast<float *>(cache);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        gg[t] = valid ? *(const f32x4 *)cache_gg(c, tile, layer, t, lane)
+                      : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        hw[t] = valid ? *(const uint2 *)cache_h(c, tile, layer, t, lane) : make_uint2(0u, 0u);
+    }
 }
 
 // Operand of the next backward matmul from dZ tiles (same slot permutation
@@ -517,8 +579,9 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
         const int64_t tile = chunk * 4 + w;
         const bool tv = tile < n_tiles;
         const int64_t s = tile * 16 + r;
-        f32x4 z[8], h[8], dz[8];
-        load_z(z, cache, tile, tv, 2, lane);
+        f32x4 gg[8], dz[8];
+        uint2 hw[8];
+        load_cache(gg, hw, cache, tile, tv, 2, lane);
         // the inputs for dW1, loaded now so that they have arrived by then
         float xin[4];
 #pragma unroll
@@ -547,12 +610,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     bsum[w][e] = t;
             }
         }
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                h[t][e] = gelu(z[t][e]);
-        stage_t(H, h, col, g);
+        stage_tb(H, hw, col, g);
         __syncthreads();
         // dW4 (rows 0..2 of tile 0), tiles over k: tk = w, w + 4
 #pragma unroll
@@ -574,7 +632,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
             const f32x4 a = mfma(sbw[t * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                dz[t][e] = a[e] * gelu_grad(z[t][e]);
+                dz[t][e] = a[e] * gg[t][e];
         }
         __syncthreads();
 
@@ -584,7 +642,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
             const int offW = layer == 2 ? OFF_W3 : OFF_W2;
             const int offB = layer == 2 ? OFF_B3 : OFF_B2;
             const int frB = layer == 2 ? FR_B3 : FR_B2;
-            load_z(z, cache, tile, tv, layer - 1, lane);  // in flight while dZ is staged
+            load_cache(gg, hw, cache, tile, tv, layer - 1, lane);  // in flight while dZ is staged
             u32x4 op[4];
             to_operand(op, dz);
             stage_t(G, dz, col, g);
@@ -596,12 +654,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     if (r == 0)
                         bsum[w][16 * t + 4 * g + e] = v;
                 }
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    h[t][e] = gelu(z[t][e]);
-            stage_t(H, h, col, g);
+            stage_tb(H, hw, col, g);
             __syncthreads();
 #pragma unroll 4
             for (int i = 0; i < 16; ++i) {
@@ -624,7 +677,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     a = mfma(sbw[(frB - FR_B4 + t * 4 + q) * 64 + lane], op[q], a);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    dz[t][e] = a[e] * gelu_grad(z[t][e]);
+                    dz[t][e] = a[e] * gg[t][e];
             }
             __syncthreads();
         }
@@ -955,7 +1008,7 @@ int sdm_mlp_forward(sdm_ctx *ctx, float *y, float *cache, const float *x, int64_
                                x, B, (const u32x4 *)w->packed, w->params);
     } else {
         // one wave per tile; inference takes two tiles at a time (larger
-        // batches only), training one, writing its pre-activations
+        // batches only), training one, writing its training cache
         const int S = cache ? 1 : 2;
         const int64_t want = (tiles + 4 * S - 1) / (4 * S);
         const int grid = (int)(want < FWD_GRID_MAX ? want : FWD_GRID_MAX);

@@ -41,7 +41,7 @@ def test_binding_covers_header(libsdm):
 
 
 def test_abi_version(libsdm):
-    assert libsdm.sdm_abi_version() == 2
+    assert libsdm.sdm_abi_version() == 3
 
 
 def test_invalid_arguments_rejected_without_gpu(libsdm):

@@ -80,7 +80,7 @@ def test_forward_matches_bf16_oracle(sdm, ctx, B):
 
 def test_training_cache_same_in_both_forward_kernels(sdm, ctx):
     """A batch above the split kernel's size goes through the one-wave-per-tile
-    kernel; its saved pre-activations of the first 16384 samples must equal
+    kernel; its training cache of the first 16384 samples must equal
     those the split kernel saves for those samples alone (the same sums)."""
     import torch
     th = _theta(5)
