@@ -779,6 +779,45 @@ struct PairCtx {
     uint32_t gbase;      // offset of the run's slots in gamma_out
 };
 
+// A kernel argument's value as an opaque uniform register (read back from
+// the first lane).  Where a value may come either from a kernel argument or
+// from a table in memory, this keeps the compiler from merging the two
+// loads into one through a private copy of the argument (a scratch store by
+// every thread).
+__device__ __forceinline__ double arg_value(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int32_t arg_value(int32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ const double *arg_value(const double *p)
+{
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (const double *)(((uint64_t)hi << 32) | lo);
+}
+
+// The single-kernel descriptor with every field an opaque uniform value.
+__device__ __forceinline__ KernelDesc arg_value(const KernelDesc &k)
+{
+    KernelDesc d;
+    d.id = arg_value(k.id);
+    d.reserved = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        d.p[i] = arg_value(k.p[i]);
+    d.table = arg_value(k.table);
+    return d;
+}
+
 template <class Args>
 __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t cs, uint32_t n_c)
 {
@@ -793,10 +832,10 @@ __device__ __forceinline__ PairCtx pair_ctx(const Args &a, int32_t c, uint32_t c
         pc.run = (uint32_t)a.seg_run[c];
         pc.gbase = a.seg_off[c] >> 1;
     } else {
-        dvc = a.dv_cell ? a.dv_cell[c] : a.dv;
-        pc.kid = a.kern.id;
+        dvc = a.dv_cell ? a.dv_cell[c] : arg_value(a.dv);
+        pc.kid = arg_value(a.kern.id);
         pc.kidx = 0;
-        pc.kp = a.kern.p[0];
+        pc.kp = arg_value(a.kern.p[0]);
         pc.run = a.run;
         pc.gbase = 0;
     }
@@ -814,7 +853,10 @@ __device__ __forceinline__ double pair_prob(const Args &a, const PairCtx &pc, ui
 {
     KernelDesc kd;
     if (pc.kid == KERNEL_TABULATED) {
-        kd = a.seg_run ? a.kernels[pc.kidx] : a.kern;
+        if (a.seg_run)
+            kd = a.kernels[pc.kidx];
+        else
+            kd = arg_value(a.kern);
     } else {
         kd.id = pc.kid;
         kd.reserved = 0;
@@ -1073,6 +1115,13 @@ __device__ __forceinline__ uint32_t local_bucket(const GroupArgs &a, int b0, int
     return b - (uint32_t)b0;
 }
 
+// The largest float not above x (x in [0, 1)).
+__device__ __forceinline__ float float_below(double x)
+{
+    const float f = (float)x;
+    return (double)f > x ? __uint_as_float(__float_as_uint(f) - 1u) : f;
+}
+
 // --------------------------------------------------------------- k_group
 // The usual fused plans (seven records per thread, 39 KB of LDS) run three
 // workgroups per CU: at most 80 VGPRs, six waves per SIMD.
@@ -1259,7 +1308,9 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         constexpr int PITER = (CAP / 2 + 2 * THREADS - 1) / (2 * THREADS);
         const uint32_t n_pairs = t_poff[nb];
         const bool one_cell = n_gc == 1;  // openers every second position
-        double phi_pre[PITER][2];
+        // kept as floats rounded down (phi_lo <= phi), so that the bound test
+        // below stays conservative; listed pairs draw phi again exactly
+        float phi_pre[PITER][2];
         if (tot > 0 && fused) {
             uint64_t rr[EPT];
             int tt[EPT];
@@ -1278,7 +1329,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 for (int u = 0; u < 2; ++u) {
                     const uint32_t k = 2 * j + (uint32_t)u;
                     valid[u] = k < n_pairs;
-                    phi_pre[it][u] = 0.0;
+                    phi_pre[it][u] = 0.0f;
                     if (!valid[u])
                         continue;
                     int bl = 0;
@@ -1294,14 +1345,14 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                     runv[0] == runv[1]) {
                     const WordPair wp = philox_words(a.seed, runv[0], step, SDM_STREAM_GAMMA,
                                                      qv[0] >> 1);
-                    phi_pre[it][0] = word_to_uniform(wp.even);
-                    phi_pre[it][1] = word_to_uniform(wp.odd);
+                    phi_pre[it][0] = float_below(word_to_uniform(wp.even));
+                    phi_pre[it][1] = float_below(word_to_uniform(wp.odd));
                 } else {
 #pragma unroll
                     for (int u = 0; u < 2; ++u)
                         if (valid[u])
-                            phi_pre[it][u] = word_to_uniform(
-                                philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u]));
+                            phi_pre[it][u] = float_below(word_to_uniform(
+                                philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u])));
                 }
             }
 #pragma unroll
@@ -1540,7 +1591,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 }
                 const PairCtx &pc = t_pc[bl];
                 const double pub = pair_bound(pc, RC[sw(f)], RC[sw(f + 1)]);
-                if (pub < phi_pre[it][u]) {  // gamma = -0.0: no collision
+                if (pub < (double)phi_pre[it][u]) {  // gamma = -0.0: no collision
                     st.pairs += 1;
                     if (a.gamma_out)
                         a.gamma_out[pc.gbase + ((rank0 + f - pc.slot_base) >> 1)] = -0.0;
