@@ -1741,6 +1741,197 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
     }
 }
 
+// --------------------------------------------------------------- k_small
+// A whole single-cell timestep in one workgroup, for launches of at most
+// SMALL_CAP SD slots (the validation box of Sec. 4 has 2^13): the Philox
+// keys, the sort by (key, s) in LDS (counting sort by the top 13 key bits,
+// then each record's exact rank within its sub-bucket by whole keys), the
+// pairs with gamma and eqs. (4)-(6), idx and the bookkeeping -- one launch
+// per step where the general path takes four, each at its launch-latency
+// floor at this size.  Results equal the general path's bit for bit.
+constexpr int SMALL_THREADS = 1024;
+constexpr int SMALL_EPT = 8;
+constexpr int SMALL_CAP = SMALL_THREADS * SMALL_EPT;
+constexpr int SMALL_SUB_SHIFT = 53 - 13;  // 2^13 = SMALL_CAP sub-buckets
+
+struct SmallArgs {
+    int64_t n_sd;
+    uint64_t *xi;
+    double *attr;
+    int32_t n_attr;
+    int64_t stride;
+    uint64_t seed;
+    uint32_t run;
+    uint32_t step;
+    const uint32_t *step_dev;
+    uint32_t *step_advance;
+    double dt;
+    const double *dv_cell;
+    double dv;
+    KernelDesc kern;
+    int slot_cell_local;
+    uint32_t *idx_out;
+    uint32_t *cell_start;
+    int64_t *n_live_out;
+    uint64_t *counters;
+    double *gamma_out;
+    // a single run: no segment tables (the pair helpers test seg_run)
+    const uint32_t *seg_off;
+    const int32_t *seg_run;
+    const int32_t *seg_kernel;
+    const double *seg_dv;
+    const KernelDesc *kernels;
+};
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_small(SmallArgs a)
+{
+    __shared__ uint64_t K[SMALL_CAP];                 // keys, by sub-bucket
+    __shared__ uint16_t S[SMALL_CAP];                 // their slots
+    __shared__ __align__(4) uint16_t H[SMALL_CAP + 2];  // sub-bucket counts, then starts
+    __shared__ uint16_t R[SMALL_CAP];                 // slot of every rank
+    __shared__ uint32_t red[5 * (SMALL_THREADS / 64) + 8];
+    uint32_t *Hw = reinterpret_cast<uint32_t *>(H);
+    const int tid = threadIdx.x;
+    const int64_t n_items = a.n_sd;
+    const uint32_t step = step_of(a.step, a.step_dev);
+    for (int i = tid; i < (SMALL_CAP + 2) / 2; i += SMALL_THREADS)
+        Hw[i] = 0;
+    // 1. keys of the live slots (two slots per Philox block), all loads of
+    //    xi in flight together
+    uint64_t key[SMALL_EPT];
+    uint32_t sb[SMALL_EPT], fp[SMALL_EPT];
+    ulonglong2 xx[SMALL_EPT / 2];
+#pragma unroll
+    for (int k = 0; k < SMALL_EPT / 2; ++k) {
+        const int64_t i0 = 2 * ((int64_t)k * SMALL_THREADS + tid);
+        xx[k] = i0 + 1 < n_items ? *reinterpret_cast<const ulonglong2 *>(a.xi + i0)
+                                 : make_ulonglong2(i0 < n_items ? a.xi[i0] : 0ull, 0ull);
+    }
+    __syncthreads();  // H cleared
+    uint32_t live_n = 0;
+#pragma unroll
+    for (int k = 0; k < SMALL_EPT / 2; ++k) {
+        const uint64_t p = (uint64_t)k * SMALL_THREADS + tid;
+        const WordPair w = philox_words(a.seed, a.run, step, SDM_STREAM_SHUFFLE, p);
+        const uint64_t kk[2] = {w.even >> 11, w.odd >> 11};
+        const uint64_t xv[2] = {xx[k].x, xx[k].y};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int j = 2 * k + e;
+            key[j] = kk[e];
+            sb[j] = 0xFFFFFFFFu;
+            fp[j] = 0;
+            if (xv[e] > 0 && (int64_t)(2 * p + e) < n_items) {
+                sb[j] = (uint32_t)(kk[e] >> SMALL_SUB_SHIFT);
+                const uint32_t sh = (sb[j] & 1u) * 16u;
+                fp[j] = (atomicAdd(&Hw[sb[j] >> 1], 1u << sh) >> sh) & 0xFFFFu;
+                ++live_n;
+            }
+        }
+    }
+    uint32_t n;
+    (void)block_exclusive_scan<SMALL_THREADS>(live_n, red, &n);
+    __syncthreads();
+    // 2. sub-bucket starts; records in sub-bucket order
+    lds_exclusive_scan16<SMALL_THREADS, SMALL_EPT>(H, SMALL_CAP, red);
+#pragma unroll
+    for (int j = 0; j < SMALL_EPT; ++j) {
+        if (sb[j] != 0xFFFFFFFFu) {
+            const uint32_t q = H[sb[j]] + fp[j];
+            K[q] = key[j];
+            S[q] = (uint16_t)(2 * ((j >> 1) * SMALL_THREADS + tid) + (j & 1));
+        }
+    }
+    __syncthreads();
+    // 3. exact ranks by (key, s) within the sub-bucket: the first RW entries
+    //    of every record's sub-bucket with independent loads (a sub-bucket
+    //    holds one record on average), the rare longer ones in a loop
+    constexpr uint32_t RW = 3;
+    uint32_t lo[SMALL_EPT], hi[SMALL_EPT];
+#pragma unroll
+    for (int j = 0; j < SMALL_EPT; ++j) {
+        const uint32_t b = sb[j] != 0xFFFFFFFFu ? sb[j] : 0u;
+        lo[j] = H[b];
+        hi[j] = sb[j] != 0xFFFFFFFFu ? H[b + 1] : lo[j];
+    }
+#pragma unroll
+    for (int j = 0; j < SMALL_EPT; ++j) {
+        const uint32_t s = 2u * ((uint32_t)(j >> 1) * SMALL_THREADS + (uint32_t)tid) + (uint32_t)(j & 1);
+        uint32_t r = lo[j];
+#pragma unroll
+        for (uint32_t i = 0; i < RW; ++i) {
+            const uint32_t q = min(lo[j] + i, (uint32_t)SMALL_CAP - 1u);
+            const uint64_t kq = K[q];
+            const uint32_t sq = S[q];
+            r += (lo[j] + i < hi[j]) && ((kq < key[j]) || (kq == key[j] && sq < s));
+        }
+        for (uint32_t q = lo[j] + RW; q < hi[j]; ++q) {
+            const uint64_t kq = K[q];
+            r += (kq < key[j]) || (kq == key[j] && (uint32_t)S[q] < s);
+        }
+        if (sb[j] != 0xFFFFFFFFu)
+            R[r] = (uint16_t)s;
+    }
+    __syncthreads();
+    // 4. idx and the cell bookkeeping
+    for (uint32_t i = tid; i < n; i += SMALL_THREADS)
+        a.idx_out[i] = R[i];
+    if (tid == 0) {
+        *a.n_live_out = (int64_t)n;
+        a.cell_start[0] = 0;
+        a.cell_start[1] = n;
+    }
+    // 5. pairs (2q, 2q + 1) of the sorted cell, two per thread sharing a
+    //    Philox block for phi
+    const PairCtx pc = pair_ctx(a, 0, 0u, n);
+    const uint32_t n_pairs = n / 2;
+    Stats st{0, 0, 0, 0, 0};
+    //    every pair's state loads issued before the first is used (the
+    //    pairs of a thread: q = 2 jb + u, jb = tid, tid + THREADS)
+    constexpr int PJ = SMALL_CAP / 4 / SMALL_THREADS;  // Philox blocks per thread
+    uint32_t ps[PJ][2][2];
+    uint64_t px[PJ][2][2];
+    double pv[PJ][2][2];
+#pragma unroll
+    for (int i = 0; i < PJ; ++i)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            // pairs past the last read slot 0 (always a slot of the launch)
+            const uint32_t q = 2 * ((uint32_t)tid + (uint32_t)i * SMALL_THREADS) + (uint32_t)u;
+            ps[i][u][0] = q < n_pairs ? (uint32_t)R[2 * q] : 0u;
+            ps[i][u][1] = q < n_pairs ? (uint32_t)R[2 * q + 1] : 0u;
+        }
+#pragma unroll
+    for (int i = 0; i < PJ; ++i)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                px[i][u][e] = a.xi[ps[i][u][e]];
+                pv[i][u][e] = a.attr[ps[i][u][e]];
+            }
+#pragma unroll
+    for (int i = 0; i < PJ; ++i) {
+        const uint32_t jb = (uint32_t)tid + (uint32_t)i * SMALL_THREADS;
+        if (2 * jb >= n_pairs)
+            continue;
+        const WordPair wp = philox_words(a.seed, a.run, step, SDM_STREAM_GAMMA, jb);
+        const double phi[2] = {word_to_uniform(wp.even), word_to_uniform(wp.odd)};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t q = 2 * jb + (uint32_t)u;
+            if (q >= n_pairs)
+                continue;
+            const double p = pair_prob(a, pc, px[i][u][0], pv[i][u][0], px[i][u][1], pv[i][u][1]);
+            finish_pair_v(a, pc, q, p, phi[u], ps[i][u][0], px[i][u][0], pv[i][u][0],
+                          ps[i][u][1], px[i][u][1], pv[i][u][1], st);
+        }
+    }
+    flush_stats<SMALL_THREADS>(st, a.counters, red);
+    if (tid == 0 && a.step_advance)
+        *a.step_advance = *a.step_advance + 1u;
+}
+
 // =================================================================== host
 static void *dalloc(Plan *p, size_t bytes)
 {
@@ -2124,6 +2315,14 @@ static void launch_tile_ept(int ept, int grid, size_t lds, hipStream_t stream, c
         launch_tile<4, LIST>(grid, lds, stream, ta);
 }
 
+// The fused single-cell launches k_small takes: the Philox keys (no
+// caller-given uniforms), no cell ids to check, at most SMALL_CAP slots.
+static bool small_step(const Plan *p, const StepInputs &in)
+{
+    return p->mode == MODE_FUSED && !p->seg_off && p->n_cell == 1 && !in.cell_id && !in.u01 &&
+           in.n_sd <= SMALL_CAP && in.n_attr >= 1;
+}
+
 void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
 {
     const bool list = p->mode != MODE_FUSED;
@@ -2133,6 +2332,36 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
         if (in.events[i])
             SDM_HIP(hipEventRecord(in.events[i], stream));
     };
+    if (small_step(p, in)) {
+        SmallArgs sa{};
+        sa.n_sd = in.n_sd;
+        sa.xi = in.xi;
+        sa.attr = in.attr;
+        sa.n_attr = in.n_attr;
+        sa.stride = in.stride;
+        sa.seed = in.seed;
+        sa.run = in.run;
+        sa.step = in.step;
+        sa.step_dev = in.step_dev;
+        sa.step_advance = in.step_advance;
+        sa.dt = in.dt;
+        sa.dv_cell = in.dv_cell;
+        sa.dv = in.dv;
+        sa.kern = in.kern;
+        sa.slot_cell_local = in.slot_cell_local ? 1 : 0;
+        sa.idx_out = in.idx_out;
+        sa.cell_start = cell_start;
+        sa.n_live_out = n_live_out;
+        sa.counters = in.counters;
+        sa.gamma_out = in.gamma_out;
+        mark(0);
+        hipLaunchKernelGGL(k_small, dim3(1), dim3(SMALL_THREADS), 0, stream, sa);
+        SDM_HIP(hipGetLastError());
+        mark(1);
+        mark(2);
+        mark(3);
+        return;
+    }
 
     TileArgs ta{};
     ta.mode = p->mode;
