@@ -464,7 +464,7 @@ def bench_ensemble(args, sdm, torch, np, workloads):
     scratch = sdm.State(xi, attr, None, len(segs))
     ctx = sdm.Context(st.n_sd, len(segs), 1)
     b = sdm.Batch(ctx, segs)
-    chosen = b.autotune(scratch, ens["dt"], sdm.rng(4, 0, 0), steps=3)
+    chosen = b.autotune(scratch, ens["dt"], sdm.rng(4, 0, 0), steps=5)
     del scratch
     step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     r = sdm.rng(4, 0, 0, step_dev=step_dev)

@@ -369,12 +369,15 @@ int sdm_batch_step(sdm_ctx *ctx, sdm_batch *b, const sdm_state *st,
 int sdm_batch_set_schedule(sdm_ctx *ctx, sdm_batch *b, int32_t schedule,
                            int32_t *n_schedules);
 
-/* Chooses the batch's block and segment schedule (key-bucket size and
- * group packing) by timing `steps` steps of each candidate on the scratch
- * state (which is advanced), or loads the choice from cache_path (a text
- * file keyed by the segment-size layout; NULL = no cache) and stores it
- * there.  Results never depend on the schedule.  Blocking.  *chosen (may
- * be NULL) receives the index of the chosen candidate. */
+/* Chooses the batch's block and segment schedule (key-bucket size, group
+ * packing, tile-kernel slots per thread) by timing each distinct candidate
+ * plan on the scratch state (which is advanced): two passes over the
+ * candidates, the second in reverse order, each a warm-up step and `steps`
+ * timed steps, the faster pass counting; or loads the choice from
+ * cache_path (a text file keyed by the segment-size layout; NULL = no
+ * cache) and stores it there.  Results never depend on the schedule.
+ * Blocking; holds every candidate plan's workspace until it returns.
+ * *chosen (may be NULL) receives the index of the chosen candidate. */
 int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch,
                  const sdm_step_params *p, int32_t steps, const char *cache_path,
                  int32_t *chosen);

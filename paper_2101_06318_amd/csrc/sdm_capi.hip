@@ -431,49 +431,68 @@ int sdm_autotune(sdm_ctx *ctx, sdm_batch *b, const sdm_state *scratch, const sdm
         SDM_HIP(hipStreamCreate(&s));
         SDM_HIP(hipEventCreate(&e0));
         SDM_HIP(hipEventCreate(&e1));
-        double best_ms = 1e300;
-        std::vector<::sdm::PlanShape> timed;
-        for (int sch = 0; sch < n_schedules(); ++sch) {
-            Plan *cand = nullptr;
-            try {
-                cand = build_batch_plan(ctx, b->segs, b->n_items, sch);
-            } catch (const ::sdm::HipError &) {
-                continue;  // this schedule does not fit the plan limits
+        // the distinct candidate plans, all kept until the choice is made
+        std::vector<std::pair<int, Plan *>> cands;
+        std::vector<::sdm::PlanShape> shapes;
+        try {
+            for (int sch = 0; sch < n_schedules(); ++sch) {
+                Plan *cand = nullptr;
+                try {
+                    cand = build_batch_plan(ctx, b->segs, b->n_items, sch);
+                } catch (const ::sdm::HipError &) {
+                    continue;  // this schedule does not fit the plan limits
+                }
+                const ::sdm::PlanShape sh = ::sdm::shape_of(cand);
+                if (std::find(shapes.begin(), shapes.end(), sh) != shapes.end()) {
+                    free_plan(cand);  // the same plan as a schedule already listed
+                    continue;
+                }
+                shapes.push_back(sh);
+                cands.emplace_back(sch, cand);
             }
-            const ::sdm::PlanShape sh = ::sdm::shape_of(cand);
-            if (std::find(timed.begin(), timed.end(), sh) != timed.end()) {
-                free_plan(cand);  // the same plan as a schedule already timed
-                continue;
-            }
-            timed.push_back(sh);
+            // two passes, the second in reverse order, each candidate a
+            // warm-up step and `steps` timed steps; a candidate's time is the
+            // faster of its two (candidates are often within a few per cent
+            // of each other, and the first steps on fresh allocations run
+            // slow)
+            std::vector<float> ms(cands.size(), 3.0e38f);
             StepInputs in;
             batch_inputs(b, scratch, p, in);
             in.gamma_out = nullptr;
             in.step_advance = nullptr;
             for (int i = 0; i < 4; ++i)
                 in.events[i] = nullptr;
-            engine_run(ctx, cand, in, s);  // warm-up
-            // the faster of two timed runs of `steps` steps (candidates are
-            // often within a few per cent of each other)
-            float ms = 3.0e38f;
-            for (int rep = 0; rep < 2; ++rep) {
-                SDM_HIP(hipEventRecord(e0, s));
-                for (int t = 0; t < steps; ++t) {
-                    in.step = p->rng.step + 1u + (uint32_t)(rep * steps + t);
-                    engine_run(ctx, cand, in, s);
+            uint32_t t_step = p->rng.step + 1u;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (size_t k = 0; k < cands.size(); ++k) {
+                    const size_t c = pass == 0 ? k : cands.size() - 1 - k;
+                    in.step = t_step++;
+                    engine_run(ctx, cands[c].second, in, s);  // warm-up
+                    SDM_HIP(hipEventRecord(e0, s));
+                    for (int t = 0; t < steps; ++t) {
+                        in.step = t_step++;
+                        engine_run(ctx, cands[c].second, in, s);
+                    }
+                    SDM_HIP(hipEventRecord(e1, s));
+                    SDM_HIP(hipEventSynchronize(e1));
+                    float rep_ms = 0.f;
+                    SDM_HIP(hipEventElapsedTime(&rep_ms, e0, e1));
+                    ms[c] = std::min(ms[c], rep_ms);
                 }
-                SDM_HIP(hipEventRecord(e1, s));
-                SDM_HIP(hipEventSynchronize(e1));
-                float rep_ms = 0.f;
-                SDM_HIP(hipEventElapsedTime(&rep_ms, e0, e1));
-                ms = std::min(ms, rep_ms);
             }
-            free_plan(cand);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = sch;
-            }
+            size_t bi = 0;
+            for (size_t c = 1; c < cands.size(); ++c)
+                if (ms[c] < ms[bi])
+                    bi = c;
+            if (!cands.empty())
+                best = cands[bi].first;
+        } catch (...) {
+            for (auto &c : cands)
+                free_plan(c.second);
+            throw;
         }
+        for (auto &c : cands)
+            free_plan(c.second);
         if (best < 0)
             throw ::sdm::HipError{hipErrorInvalidValue, "no schedule fits this batch"};
         if (cache_path) {
