@@ -541,14 +541,65 @@ __device__ inline void to_operand(u32x4 (&op)[4], const f32x4 (&d)[8])
                       pack2(d[2 * q + 1][2], d[2 * q + 1][3])};
 }
 
-// Backward pass over chunks of 64 samples (4 tiles, one per wave); each
-// workgroup accumulates its chunks into its own row of `part`.
-__global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
-                                                      const float *__restrict__ dy,
-                                                      const float *__restrict__ x,
-                                                      const float *__restrict__ cache, int64_t B,
-                                                      const u32x4 *__restrict__ packed,
-                                                      int64_t n_chunks)
+// Backward pass over chunks of 64 samples; each workgroup accumulates its
+// chunks into its own row of `part`.  Eight waves: waves 0-3 each carry one
+// 16-sample tile down the layers (dZ in registers, the transposed products
+// on the matrix cores); all eight share each layer's weight-gradient tiles
+// (LDS operands).  The next layer's cache entries are loaded while the
+// current layer's gradient tiles run.
+constexpr int BWD_THREADS = 512;
+constexpr int BWD_W = BWD_THREADS / 64;
+
+// The cached bf16 activations of one layer of a tile, into LDS rows.
+__device__ inline void load_h(uint2 (&hw)[8], const float *__restrict__ cache, int64_t tile,
+                              bool valid, int layer, int lane)
+{
+    float *c = const_cast<float *>(cache);
+    const int64_t tc = valid ? tile : 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        hw[t] = *(const uint2 *)cache_h(c, tc, layer, t, lane);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        hw[t] = valid ? hw[t] : make_uint2(0u, 0u);
+}
+
+__device__ inline void load_gg(f32x4 (&gg)[8], const float *__restrict__ cache, int64_t tile,
+                               bool valid, int layer, int lane)
+{
+    float *c = const_cast<float *>(cache);
+    const int64_t tc = valid ? tile : 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        gg[t] = *(const f32x4 *)cache_gg(c, tc, layer, t, lane);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+        gg[t] = valid ? gg[t] : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+// The 64 gradient tiles (16 x 16) of a 128 x 128 weight matrix, shared by
+// the workgroup's waves, from the staged G (dZ^T) and H (A^T).
+__device__ inline void dw_tiles_128(float *prow, int offW, bool first, const uint16_t *G,
+                                    const uint16_t *H, int w, int lane)
+{
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll 2
+    for (int i = 0; i < 64 / BWD_W; ++i) {
+        const int idx = w + BWD_W * i, tn = idx >> 3, tk = idx & 7;
+        const f32x4 a = dw_tile(G, H, tn, tk, lane);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            put(prow + offW + (16 * tn + 4 * g + e) * NH + 16 * tk + r, first, a[e]);
+    }
+}
+
+__global__ __launch_bounds__(BWD_THREADS) void k_mlp_backward(float *__restrict__ part,
+                                                              const float *__restrict__ dy,
+                                                              const float *__restrict__ x,
+                                                              const float *__restrict__ cache,
+                                                              int64_t B,
+                                                              const u32x4 *__restrict__ packed,
+                                                              int64_t n_chunks)
 {
     __shared__ __attribute__((aligned(16))) uint16_t G[NH * BWD_ROW];
     __shared__ __attribute__((aligned(16))) uint16_t H[NH * BWD_ROW];
@@ -556,66 +607,75 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
     // the transposed-weight fragments (B4, B3, B2: 72 KiB) in LDS, staged
     // once with all of a thread's loads in flight
     constexpr int NBF = (FR_N - FR_B4) * 64;
-    static_assert(NBF % 256 == 0, "fragments per thread");
+    static_assert(NBF % BWD_THREADS == 0, "fragments per thread");
     __shared__ u32x4 sbw[NBF];
     {
-        u32x4 rr[NBF / 256];
+        u32x4 rr[NBF / BWD_THREADS];
 #pragma unroll
-        for (int j = 0; j < NBF / 256; ++j)
-            rr[j] = packed[FR_B4 * 64 + threadIdx.x + 256 * j];
+        for (int j = 0; j < NBF / BWD_THREADS; ++j)
+            rr[j] = packed[FR_B4 * 64 + threadIdx.x + BWD_THREADS * j];
 #pragma unroll
-        for (int j = 0; j < NBF / 256; ++j)
-            sbw[threadIdx.x + 256 * j] = rr[j];
+        for (int j = 0; j < NBF / BWD_THREADS; ++j)
+            sbw[threadIdx.x + BWD_THREADS * j] = rr[j];
     }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-    const int col = 16 * w + r;
+    const bool chain = w < 4;  // waves 0-3: one tile each
+    const int col = 16 * (w & 3) + r;
     const int64_t n_tiles = (B + 15) / 16;
     float *prow = part + (int64_t)blockIdx.x * NPARAM;
 
     for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         const bool first = chunk == blockIdx.x;
-        const int64_t tile = chunk * 4 + w;
+        const int64_t tile = chunk * 4 + (w & 3);
         const bool tv = tile < n_tiles;
         const int64_t s = tile * 16 + r;
-        f32x4 gg[8], dz[8];
+        f32x4 gg[8], gn[8], dz[8];
         uint2 hw[8];
-        load_cache(gg, hw, cache, tile, tv, 2, lane);
-        // the inputs for dW1, loaded now so that they have arrived by then
-        float xin[4];
+        float xin[4], d4[NOUT];
+        if (chain) {
+            load_gg(gg, cache, tile, tv, 2, lane);
+            load_h(hw, cache, tile, tv, 2, lane);
+            const int64_t sc = s < B ? s : 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = 4 * g + e;
-            xin[e] = (k < NIN && s < B) ? x[s * NIN + (k < NIN ? k : 0)] : 0.0f;
-        }
+            for (int e = 0; e < 4; ++e)
+                xin[e] = x[sc * NIN + min(4 * g + e, NIN - 1)];
+#pragma unroll
+            for (int e = 0; e < NOUT; ++e)
+                d4[e] = dy[sc * NOUT + e];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                xin[e] = (4 * g + e < NIN && s < B) ? xin[e] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < NOUT; ++e)
+                d4[e] = s < B ? d4[e] : 0.0f;
 
-        // ---- layer 4: dZ4 = dy
-        float d4[NOUT];
+            // ---- layer 4: dZ4 = dy
 #pragma unroll
-        for (int e = 0; e < NOUT; ++e)
-            d4[e] = s < B ? dy[s * NOUT + e] : 0.0f;
-        const u32x4 op4 = g == 0 ? u32x4{pack2(d4[0], d4[1]), pack2(d4[2], 0.0f), 0u, 0u}
-                                 : u32x4{0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int n = 4 * g + e;
-            G[n * BWD_ROW + col] = n < NOUT ? (uint16_t)bf16_bits(d4[n < NOUT ? n : 0]) : 0;
-        }
-        if (g == 0) {
-#pragma unroll
-            for (int e = 0; e < NOUT; ++e) {
-                const float t = sum16(d4[e]);
-                if (r == 0)
-                    bsum[w][e] = t;
+            for (int e = 0; e < 4; ++e) {
+                const int n = 4 * g + e;
+                G[n * BWD_ROW + col] = n < NOUT ? (uint16_t)bf16_bits(d4[n < NOUT ? n : 0]) : 0;
             }
-        }
-        stage_tb(H, hw, col, g);
-        __syncthreads();
-        // dW4 (rows 0..2 of tile 0), tiles over k: tk = w, w + 4
+            if (g == 0) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int tk = w + 4 * i;
+                for (int e = 0; e < NOUT; ++e) {
+                    const float t = sum16(d4[e]);
+                    if (r == 0)
+                        bsum[w][e] = t;
+                }
+            }
+            stage_tb(H, hw, col, g);
+        }
+        __syncthreads();
+        // the next layer's cache entries, in flight during the tiles below
+        if (chain) {
+            load_gg(gn, cache, tile, tv, 1, lane);
+            load_h(hw, cache, tile, tv, 1, lane);
+        }
+        // dW4 (rows 0..2 of tile 0): column tile tk = w
+        {
+            const int tk = w;
             const f32x4 a = dw_tile(G, H, 0, tk, lane);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -627,24 +687,70 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                 ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
                     bsum[3][threadIdx.x]);
         // dH3 = W4^T dZ4, dZ3 = dH3 * GELU'(z3)
+        if (chain) {
+            const u32x4 op4 = g == 0 ? u32x4{pack2(d4[0], d4[1]), pack2(d4[2], 0.0f), 0u, 0u}
+                                     : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const f32x4 a = mfma(sbw[t * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+            for (int t = 0; t < 8; ++t) {
+                const f32x4 a = mfma(sbw[t * 64 + lane], op4, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                dz[t][e] = a[e] * gg[t][e];
+                for (int e = 0; e < 4; ++e)
+                    dz[t][e] = a[e] * gg[t][e];
+            }
         }
         __syncthreads();
 
-        // ---- layers 3 and 2
-#pragma unroll 1
+        // ---- layers 3 and 2 (weights W3, then W2)
+#pragma unroll
         for (int layer = 2; layer >= 1; --layer) {
             const int offW = layer == 2 ? OFF_W3 : OFF_W2;
             const int offB = layer == 2 ? OFF_B3 : OFF_B2;
             const int frB = layer == 2 ? FR_B3 : FR_B2;
-            load_cache(gg, hw, cache, tile, tv, layer - 1, lane);  // in flight while dZ is staged
             u32x4 op[4];
-            to_operand(op, dz);
+            if (chain) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    gg[t] = gn[t];
+                to_operand(op, dz);
+                stage_t(G, dz, col, g);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v = sum16(dz[t][e]);
+                        if (r == 0)
+                            bsum[w][16 * t + 4 * g + e] = v;
+                    }
+                stage_tb(H, hw, col, g);
+            }
+            __syncthreads();
+            if (chain && layer == 2) {  // the first layer's entries for the next round
+                load_gg(gn, cache, tile, tv, 0, lane);
+                load_h(hw, cache, tile, tv, 0, lane);
+            }
+            dw_tiles_128(prow, offW, first, G, H, w, lane);
+            if (threadIdx.x < NH)
+                put(prow + offB + threadIdx.x, first,
+                    ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
+                        bsum[3][threadIdx.x]);
+            // dH = W^T dZ, dZ(prev) = dH * GELU'(z(prev))
+            if (chain) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    f32x4 a{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        a = mfma(sbw[(frB - FR_B4 + t * 4 + q) * 64 + lane], op[q], a);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        dz[t][e] = a[e] * gg[t][e];
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- layer 1: dW1 = dZ1^T x (row tile tn = w)
+        if (chain) {
             stage_t(G, dz, col, g);
 #pragma unroll
             for (int t = 0; t < 8; ++t)
@@ -654,51 +760,13 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
                     if (r == 0)
                         bsum[w][16 * t + 4 * g + e] = v;
                 }
-            stage_tb(H, hw, col, g);
-            __syncthreads();
-#pragma unroll 4
-            for (int i = 0; i < 16; ++i) {
-                const int idx = w + 4 * i, tn = idx >> 3, tk = idx & 7;
-                const f32x4 a = dw_tile(G, H, tn, tk, lane);
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    put(prow + offW + (16 * tn + 4 * g + e) * NH + 16 * tk + r, first, a[e]);
-            }
-            if (threadIdx.x < NH)
-                put(prow + offB + threadIdx.x, first,
-                    ((bsum[0][threadIdx.x] + bsum[1][threadIdx.x]) + bsum[2][threadIdx.x]) +
-                        bsum[3][threadIdx.x]);
-            // dH = W^T dZ, dZ(prev) = dH * GELU'(z(prev))
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                f32x4 a{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    a = mfma(sbw[(frB - FR_B4 + t * 4 + q) * 64 + lane], op[q], a);
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    dz[t][e] = a[e] * gg[t][e];
-            }
-            __syncthreads();
+            for (int e = 0; e < 4; ++e)
+                H[(4 * g + e) * BWD_ROW + col] = (uint16_t)bf16_bits(xin[e]);
         }
-
-        // ---- layer 1: dW1 = dZ1^T x
-        stage_t(G, dz, col, g);
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = sum16(dz[t][e]);
-                if (r == 0)
-                    bsum[w][16 * t + 4 * g + e] = v;
-            }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            H[(4 * g + e) * BWD_ROW + col] = (uint16_t)bf16_bits(xin[e]);
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int tn = w + 4 * i;
+        {
+            const int tn = w;
             const f32x4 a = dw_tile(G, H, tn, 0, lane);
             if (r < NIN) {
 #pragma unroll
@@ -714,18 +782,28 @@ __global__ __launch_bounds__(256) void k_mlp_backward(float *__restrict__ part,
     }
 }
 
-__global__ void k_mlp_reduce(float *__restrict__ grad, const float *__restrict__ part, int rows)
+// grad[i] = sum over the partial rows: four threads per parameter each sum
+// a quarter of the rows in order, then ((q0 + q1) + q2) + q3 (a fixed
+// order: deterministic).
+constexpr int RED_SPLIT = 4;
+__global__ __launch_bounds__(256) void k_mlp_reduce(float *__restrict__ grad,
+                                                    const float *__restrict__ part, int rows)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NPARAM)
-        return;
-    // the rows in a fixed order; unrolled so that eight loads are in flight
-    // ahead of their (ordered) additions
+    __shared__ float qs[RED_SPLIT][64];
+    const int j = threadIdx.x & 63, h = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + j;
+    const int per = (rows + RED_SPLIT - 1) / RED_SPLIT;
+    const int w0 = h * per, w1 = min(rows, w0 + per);
     float acc = 0.0f;
+    if (i < NPARAM) {
 #pragma unroll 8
-    for (int w = 0; w < rows; ++w)
-        acc += part[(int64_t)w * NPARAM + i];
-    grad[i] = acc;
+        for (int w = w0; w < w1; ++w)
+            acc += part[(int64_t)w * NPARAM + i];
+    }
+    qs[h][j] = acc;
+    __syncthreads();
+    if (h == 0 && i < NPARAM)
+        grad[i] = ((qs[0][j] + qs[1][j]) + qs[2][j]) + qs[3][j];
 }
 
 __global__ __launch_bounds__(1024) void k_mlp_mse(float *__restrict__ dy, float *__restrict__ loss,
@@ -1045,10 +1123,10 @@ int sdm_mlp_backward(sdm_ctx *ctx, float *grad, const float *dy, const float *x,
         ctx->mlp_part_rows = rows;
     }
     if (rows > 0)
-        hipLaunchKernelGGL(k_mlp_backward, dim3(rows), dim3(256), 0, stream, ctx->mlp_part, dy,
-                           x, cache, B, (const u32x4 *)w->packed, chunks);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(NPARAM, 256)), dim3(256), 0, stream, grad,
-                       ctx->mlp_part, rows);
+        hipLaunchKernelGGL(k_mlp_backward, dim3(rows), dim3(BWD_THREADS), 0, stream,
+                           ctx->mlp_part, dy, x, cache, B, (const u32x4 *)w->packed, chunks);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(NPARAM, 64)), dim3(64 * RED_SPLIT), 0, stream,
+                       grad, ctx->mlp_part, rows);
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }
