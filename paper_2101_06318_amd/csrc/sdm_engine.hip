@@ -519,6 +519,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         }
     }
 
+    int ti_prev = 0;  // the run of this thread's previous slot pair (LDS table row)
 #pragma unroll
     for (int k = 0; k < EPT / 2; ++k) {
         const int64_t p = pair0 + (int64_t)k * THREADS + tid;
@@ -569,7 +570,11 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
         if (seg_n > 0) {
             // the two slots of a pair share a run (runs start at even slots);
             // slots past a run's length (alignment padding) belong to none
-            ti = upper_index(st_off, seg_n, s[0]);
+            // a thread's slots grow with k: search on from its last run
+            // (one LDS read while the run goes on)
+            if (ti_prev + 1 < seg_n && st_off[ti_prev + 1] <= s[0])
+                ti_prev += 1 + upper_index(st_off + ti_prev + 1, seg_n - ti_prev - 1, s[0]);
+            ti = ti_prev;
             seg = st_first + ti;
             cell[0] = cell[1] = seg;
 #pragma unroll
