@@ -1863,12 +1863,19 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small(SmallArgs a)
     for (int j = 0; j < SMALL_EPT; ++j) {
         const uint32_t s = 2u * ((uint32_t)(j >> 1) * SMALL_THREADS + (uint32_t)tid) + (uint32_t)(j & 1);
         uint32_t r = lo[j];
+        uint64_t kq[RW];
+        uint32_t sq[RW];
+#pragma unroll
+        for (uint32_t i = 0; i < RW; ++i) {  // loads first, no branches
+            const uint32_t q = min(lo[j] + i, (uint32_t)SMALL_CAP - 1u);
+            kq[i] = K[q];
+            sq[i] = S[q];
+        }
 #pragma unroll
         for (uint32_t i = 0; i < RW; ++i) {
-            const uint32_t q = min(lo[j] + i, (uint32_t)SMALL_CAP - 1u);
-            const uint64_t kq = K[q];
-            const uint32_t sq = S[q];
-            r += (lo[j] + i < hi[j]) && ((kq < key[j]) || (kq == key[j] && sq < s));
+            const uint32_t lt = (uint32_t)(kq[i] < key[j]) |
+                                ((uint32_t)(kq[i] == key[j]) & (uint32_t)(sq[i] < s));
+            r += (lo[j] + i < hi[j]) ? lt : 0u;
         }
         for (uint32_t q = lo[j] + RW; q < hi[j]; ++q) {
             const uint64_t kq = K[q];
