@@ -482,27 +482,38 @@ def bench_ensemble(args, sdm, torch, np, workloads):
         gms = None if args.eager else graph_ms(torch, run_step, args.steps, stream)
         return total_ms, kms, gms, c0, c1
 
-    # the schedule the library uses without tuning (0), then the tuned one
-    b.set_schedule(0)
-    d_total, d_kms, d_gms, _, _ = measure()
-    b.set_schedule(chosen)
-    total_ms, kms, gms, c0, c1 = measure()
+    # the schedule the library uses without tuning (0) and the autotuner's
+    # choice, each timed here the same way; the line reports the faster
+    # (the autotuner times eager steps on a scratch copy, and candidates are
+    # often within a few per cent of each other) and both
     K = args.steps
-    pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
-    f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
+    meas = {}
+    for sch in ([0] if chosen == 0 else [0, chosen]):
+        b.set_schedule(sch)
+        total_ms, kms, gms, c0, c1 = measure()
+        pairs = int(c1[sdm.CNT_PAIRS] - c0[sdm.CNT_PAIRS]) / K
+        f_coll = int(c1[sdm.CNT_COLLISIONS] - c0[sdm.CNT_COLLISIONS]) / max(pairs * K, 1)
+        step_ms = gms if gms else total_ms / K
+        meas[sch] = dict(total_ms=total_ms, kms=kms, gms=gms, pairs=pairs, f_coll=f_coll,
+                         step_ms=step_ms)
     assert ctx.read_errors() == 0
+    best = min(meas, key=lambda k: meas[k]["step_ms"])
+    m = meas[best]
+    total_ms, kms, gms, pairs, f_coll, step_ms = (m["total_ms"], m["kms"], m["gms"], m["pairs"],
+                                                  m["f_coll"], m["step_ms"])
     b_alg = algorithmic_bytes(pairs, f_coll, 48.0, 32.0)
     workload = "ensemble_1024"
-    step_ms = gms if gms else total_ms / K
-    d_step_ms = d_gms if d_gms else d_total / K
     out = base_line("SDM pair-steps/s, 1024-run batched ensemble", pairs / (step_ms / 1e3),
                     "pair-steps/s", K, args.warmup, step_ms, "f64",
                     {"workload": workload, "runs": len(segs), "n_sd": int(sum(s[1] for s in segs)),
                      "kernels": "golovin (even runs), geometric (odd runs)", "dt_s": ens["dt"],
-                     "seed": 4, "schedule": chosen, "pairs_per_step": pairs,
-                     "collision_fraction": f_coll, "timing": TIMING if gms else TIMING_EAGER})
-    out["default_schedule"] = {"schedule": 0, "ms_per_step": d_step_ms,
-                               "value": pairs / (d_step_ms / 1e3), "kernel_ms": d_kms}
+                     "seed": 4, "schedule": best, "autotuned_schedule": chosen,
+                     "pairs_per_step": pairs, "collision_fraction": f_coll,
+                     "timing": TIMING if gms else TIMING_EAGER})
+    for key, sch in (("default_schedule", 0), ("autotuned_schedule", chosen)):
+        out[key] = {"schedule": sch, "ms_per_step": meas[sch]["step_ms"],
+                    "value": meas[sch]["pairs"] / (meas[sch]["step_ms"] / 1e3),
+                    "kernel_ms": meas[sch]["kms"]}
     out["roofline"] = roofline(b_alg, kms, workload)
     out["kernel_ms"] = kms
     out["graph_ms_per_step"] = gms
@@ -1002,7 +1013,7 @@ def main():
 
 SUB_KEYS = ("metric", "value", "unit", "ms_per_step", "dtype", "config", "kernel_ms",
             "roofline", "step_roofline", "cell_steps_per_s", "sdm_cell_steps_per_s",
-            "speedup_vs_sdm", "default_schedule", "golovin_moments_16_seeds",
+            "speedup_vs_sdm", "default_schedule", "autotuned_schedule", "golovin_moments_16_seeds",
             "golovin_within_tolerance", "golovin_tolerance", "wall_s_3600_steps",
             "surrogate_gate", "methods")
 
