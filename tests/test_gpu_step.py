@@ -226,6 +226,43 @@ def test_graph_replay_matches_eager(sdm):
     ctx.close()
 
 
+def test_small_launch_graph_replay_and_attributes(sdm):
+    """Single-cell launches of at most 8192 slots run as one workgroup: its
+    step under graph replay (device step counter advanced by the graph)
+    equals the eager steps, and with four attribute rows, a per-cell volume
+    array and gamma it matches the oracle element by element."""
+    import torch
+    n_sd = 8000
+    w = workloads.box(n_sd, seed=14)
+    k = sdm.kernel(0, [1500.0 * 100])
+    ctx = sdm.Context(n_sd, 1, 1)
+    a = sdm.State(w["xi"], w["attr"], None, 1)
+    b = sdm.State(w["xi"], w["attr"], None, 1)
+    step_dev = dev(np.array([0], np.uint32))
+    s = torch.cuda.Stream()
+    ctx.prepare_step(b, 1.0, k, sdm.rng(14, 0, 0, step_dev=step_dev), dv=w["dv"][0])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ctx.step(b, 1.0, k, sdm.rng(14, 0, 0, step_dev=step_dev), dv=w["dv"][0],
+                     step_advance=step_dev, stream=s)
+    _sync()
+    for t in range(5):
+        ctx.step(a, 1.0, k, sdm.rng(14, 0, t), dv=w["dv"][0])
+        _sync()
+        g.replay()
+        _sync()
+        for name in ("xi", "attr", "idx", "n_live", "cell_start", "counters"):
+            assert np.array_equal(host(getattr(a, name)), host(getattr(b, name))), (t, name)
+        assert int(host(step_dev)[0]) == t + 1
+    assert int(host(a.counters)[sdm.CNT_COLLISIONS]) > 0
+    ctx.close()
+    w4 = workloads.with_extra_attributes(workloads.box(5000, seed=15), 4)
+    ctx4 = sdm.Context(5000, 1, 4)
+    _run_pair(sdm, ctx4, w4, 3, seed=15, kparams=[1500.0 * 100], gamma=True)
+    ctx4.close()
+
+
 def test_run_twice_deterministic(sdm):
     import torch
     w = workloads.grid(seed=11, nx=16, ny=16)
