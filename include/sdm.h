@@ -461,7 +461,9 @@ int sdm_mlp_mse(sdm_ctx *ctx, float *dy, float *loss, const float *y, const floa
                 int64_t B, hipStream_t stream);
 
 /* One Adam step (Kingma & Ba) on w->params from grad, updating opt->m,
- * opt->v, then repacking w->packed. */
+ * opt->v and, in the same kernel, each updated weight's bf16 copies in
+ * w->packed (w->packed must hold a pack of the network, whose padding the
+ * pack wrote: sdm_mlp_pack once after writing w->params). */
 int sdm_mlp_adam(sdm_ctx *ctx, const sdm_mlp *w, const sdm_mlp_opt *opt, const float *grad,
                  const sdm_adam_hp *hp, hipStream_t stream);
 

@@ -834,8 +834,49 @@ struct AdamF {
     float lr, b1, omb1, b2, omb2, eps, c1, c2;  // omb = 1 - beta, c = 1 / (1 - beta^t)
 };
 
+// Slot p (0..31) of a K-step whose neuron is 32q + k32: the inverse of
+// perm32.
+__device__ inline int perm32_inv(int k32)
+{
+    const int k = k32 < 16 ? k32 : k32 - 16;
+    return 8 * (k >> 2) + (k & 3) + (k32 < 16 ? 0 : 4);
+}
+
+// Packed bf16 element of fragment f, lane l = r + 16 (p >> 3), slot p & 7.
+__device__ inline int packed_index(int f, int r, int p)
+{
+    return f * 512 + (r + 16 * (p >> 3)) * 8 + (p & 7);
+}
+
+// The packed elements (up to two: a forward and a transposed fragment) of
+// master weight i; -1 where there is none (biases are not packed).  The
+// inverse of pack_source.
+__device__ inline void packed_of(int i, int &j0, int &j1)
+{
+    j0 = j1 = -1;
+    if (i < OFF_B1) {  // W1 [128][5]: F1, K = the input feature
+        const int n = i / NIN, k = i % NIN;
+        j0 = packed_index(FR_F1 + (n >> 4), n & 15, k);
+    } else if (i >= OFF_W2 && i < OFF_B2) {  // W2 [128][128]: F2 and B2
+        const int n = (i - OFF_W2) / NH, k = (i - OFF_W2) % NH;
+        j0 = packed_index(FR_F2 + (n >> 4) * 4 + (k >> 5), n & 15, perm32_inv(k & 31));
+        j1 = packed_index(FR_B2 + (k >> 4) * 4 + (n >> 5), k & 15, perm32_inv(n & 31));
+    } else if (i >= OFF_W3 && i < OFF_B3) {  // W3: F3 and B3
+        const int n = (i - OFF_W3) / NH, k = (i - OFF_W3) % NH;
+        j0 = packed_index(FR_F3 + (n >> 4) * 4 + (k >> 5), n & 15, perm32_inv(k & 31));
+        j1 = packed_index(FR_B3 + (k >> 4) * 4 + (n >> 5), k & 15, perm32_inv(n & 31));
+    } else if (i >= OFF_W4 && i < OFF_B4) {  // W4 [3][128]: F4 and B4
+        const int o = (i - OFF_W4) / NH, k = (i - OFF_W4) % NH;
+        j0 = packed_index(FR_F4 + (k >> 5), o, perm32_inv(k & 31));
+        j1 = packed_index(FR_B4 + (k >> 4), k & 15, o);
+    }
+}
+
+// One Adam step per master weight, whose bf16 copies in the packed
+// fragments are rewritten at once (the padding keeps the zeros the first
+// pack wrote).
 __global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
-                           const float *__restrict__ grad, AdamF h)
+                           uint16_t *__restrict__ packed, const float *__restrict__ grad, AdamF h)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAM)
@@ -845,7 +886,15 @@ __global__ void k_mlp_adam(float *__restrict__ P, float *__restrict__ m, float *
     const float vi = h.b2 * v[i] + h.omb2 * (gi * gi);
     m[i] = mi;
     v[i] = vi;
-    P[i] = P[i] - h.lr * (mi * h.c1) / (sqrtf(vi * h.c2) + h.eps);
+    const float pi = P[i] - h.lr * (mi * h.c1) / (sqrtf(vi * h.c2) + h.eps);
+    P[i] = pi;
+    int j0, j1;
+    packed_of(i, j0, j1);
+    const uint16_t b = (uint16_t)bf16_bits(pi);
+    if (j0 >= 0)
+        packed[j0] = b;
+    if (j1 >= 0)
+        packed[j1] = b;
 }
 
 struct Box5 {
@@ -1163,9 +1212,7 @@ int sdm_mlp_adam(sdm_ctx *ctx, const sdm_mlp *w, const sdm_mlp_opt *opt, const f
     h.c1 = (float)(1.0 / (1.0 - pow(hp->beta1, (double)hp->t)));
     h.c2 = (float)(1.0 / (1.0 - pow(hp->beta2, (double)hp->t)));
     hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(NPARAM, 256)), dim3(256), 0, stream, w->params,
-                       opt->m, opt->v, grad, h);
-    hipLaunchKernelGGL(k_mlp_pack, dim3(grid_for(FR_N * 256, 256)), dim3(256), 0, stream,
-                       (uint32_t *)w->packed, (const float *)w->params);
+                       opt->m, opt->v, (uint16_t *)w->packed, grad, h);
     SDM_HIP(hipGetLastError());
     SDM_CATCH
 }

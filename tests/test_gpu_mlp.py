@@ -167,8 +167,11 @@ def test_adam_matches_oracle_and_repacks(sdm, ctx):
     # float32 moments vs float64: terms of size <= 0.1 |g| <= 0.1, rounding ~1e-8 each
     assert np.allclose(host(m), m64, rtol=1e-5, atol=1e-7)
     assert np.allclose(host(v), v64, rtol=1e-5, atol=1e-9)
-    # the packed copy follows the masters
+    # the packed copy follows the masters: the same bits as a fresh pack,
+    # the transposed fragments of the backward pass included
     fresh = sdm.Mlp(ctx, got)
+    _sync()
+    assert np.array_equal(host(net.packed), host(fresh.packed))
     x = dev(_x(77))
     y1 = torch.zeros((77, 3), dtype=torch.float32, device="cuda")
     y2 = torch.zeros_like(y1)
