@@ -279,6 +279,54 @@ __device__ __forceinline__ void lds_exclusive_scan(uint32_t *arr, int n, uint32_
     __syncthreads();
 }
 
+// In-place exclusive scan of arr[0..n) in LDS for large n; returns the total.
+// Each wave takes a contiguous run of 64-entry rows and scans it a row at a
+// time, so a wave's accesses cover 64 consecutive words (one per bank) rather
+// than one word per lane a whole chunk apart.  The caller puts a barrier
+// between the return and the next use of arr or scratch.
+template <int THREADS>
+__device__ __forceinline__ uint32_t lds_scan_rows(uint32_t *arr, int n, uint32_t *scratch)
+{
+    constexpr int W = THREADS / 64, U = 4;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int rows = (n + 63) >> 6;
+    const int per = (rows + W - 1) / W;
+    const int r0 = min(rows, wid * per), r1 = min(rows, r0 + per);
+    uint32_t s = 0;
+    for (int r = r0; r < r1; ++r) {
+        const int i = r * 64 + lane;
+        s += i < n ? arr[i] : 0u;
+    }
+    s = wave_scan_u32(s);
+    if (lane == 63)
+        scratch[wid] = s;
+    __syncthreads();
+    uint32_t run = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t t = scratch[w];
+        run += w < wid ? t : 0u;
+        all += t;
+    }
+    for (int r = r0; r < r1; r += U) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (r + u) * 64 + lane;
+            v[u] = r + u < r1 && i < n ? arr[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (r + u) * 64 + lane;
+            const uint32_t inc = wave_scan_u32(v[u]);
+            if (r + u < r1 && i < n)
+                arr[i] = run + inc - v[u];
+            run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        }
+    }
+    return all;
+}
+
 // lds_exclusive_scan on 16-bit entries (every sum below 2^16).
 template <int THREADS, int PER>
 __device__ __forceinline__ void lds_exclusive_scan16(uint16_t *arr, int n, uint32_t *scratch)
@@ -663,18 +711,7 @@ __global__ __launch_bounds__(THREADS) void k_tile(TileArgs a)
     __syncthreads();
     // exclusive bucket offsets of this tile
     {
-        const int chunk = (NB + THREADS - 1) / THREADS;
-        const int lo = min(NB, tid * chunk), hi = min(NB, lo + chunk);
-        uint32_t sum = 0;
-        for (int b = lo; b < hi; ++b)
-            sum += hist[b];
-        uint32_t total;
-        uint32_t run = block_exclusive_scan<THREADS>(sum, scan_scratch, &total);
-        for (int b = lo; b < hi; ++b) {
-            const uint32_t c = hist[b];
-            hist[b] = run;
-            run += c;
-        }
+        const uint32_t total = lds_scan_rows<THREADS>(hist, NB, scan_scratch);
         if (tid == 0) {
             hist[NB] = total;
             if (total)
