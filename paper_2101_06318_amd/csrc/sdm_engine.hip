@@ -1167,7 +1167,7 @@ __device__ __forceinline__ float float_below(double x)
 // --------------------------------------------------------------- k_group
 // The usual fused plans (seven records per thread, 39 KB of LDS) run three
 // workgroups per CU: at most 80 VGPRs, six waves per SIMD.
-template <int THREADS, int EPT, bool FUSED>
+template <int THREADS, int EPT, bool FUSED, bool ONE_CELL = false>
 __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
@@ -1182,6 +1182,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     __shared__ PairCtx t_pc[MAXB];
     __shared__ uint32_t t_pa[MAXB];        // first opener position of each bucket
     __shared__ uint32_t t_poff[MAXB + 1];  // pairs of the buckets before
+    __shared__ uint8_t pair_bl[FUSED && !ONE_CELL ? CAP / 2 : 1];  // bucket of each pair
     // cells of the group (c_lo + i): first bucket, key bits, run and, for
     // batches, first SD slot
     __shared__ uint32_t g_cbb[MAXB];
@@ -1349,7 +1350,8 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         // it THREADS), drawn while the records are in flight
         constexpr int PITER = (CAP / 2 + 2 * THREADS - 1) / (2 * THREADS);
         const uint32_t n_pairs = t_poff[nb];
-        const bool one_cell = n_gc == 1;  // openers every second position
+        // openers every second position (ONE_CELL: a single-cell launch)
+        const bool one_cell = ONE_CELL || n_gc == 1;
         // kept as floats rounded down (phi_lo <= phi), so that the bound test
         // below stays conservative; listed pairs draw phi again exactly
         float phi_pre[PITER][2];
@@ -1380,6 +1382,8 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                         bl = upper_index(t_poff, nb, k);
                         f = t_pa[bl] + 2u * (k - t_poff[bl]);
                     }
+                    if (!one_cell)
+                        pair_bl[k] = (uint8_t)bl;
                     runv[u] = t_pc[bl].run;
                     qv[u] = (rank0 + f - t_pc[bl].slot_base) >> 1;
                 }
@@ -1628,7 +1632,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 int bl = 0;
                 uint32_t f = t_pa[0] + 2u * k;
                 if (!one_cell) {
-                    bl = upper_index(t_poff, nb, k);
+                    bl = pair_bl[k];
                     f = t_pa[bl] + 2u * (k - t_poff[bl]);
                 }
                 const PairCtx &pc = t_pc[bl];
@@ -2538,11 +2542,18 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.group_tot = p->group_tot;
     ga.group_stats = p->group_stats;
     mark(1);
-    if (p->gept == GROUP_EPT_L && !list)
+    const bool one = p->n_cell == 1;
+    if (p->gept == GROUP_EPT_L && !list && one)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true, true>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (p->gept == GROUP_EPT_L && !list)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     else if (p->gept == GROUP_EPT_L)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, false>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (!list && one)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true, true>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     else if (!list)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true>), dim3(p->G),
