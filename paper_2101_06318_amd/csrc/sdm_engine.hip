@@ -1199,7 +1199,9 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     // afterwards the fused mode's bound codes in sorted order (their ids go
     // to the sub-bucket table, dead by then)
     constexpr int POOL = FUSED ? 8 * CAP : 12 * CAP;
-    __shared__ __align__(16) unsigned char pool[POOL];
+    // (32 bytes past the end: the rank windows read up to RW - 1 = 3
+    // entries past the last one, unclamped, and ignore them)
+    __shared__ __align__(16) unsigned char pool[POOL + 32];
     static_assert(CAP < 65536, "16-bit sub-bucket sums and candidate positions");
     static_assert(2 * (NSUB + 2) >= 4 * (CAP / 2), "candidate list fits the sub-bucket table");
     static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= POOL,
@@ -1474,30 +1476,37 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const uint32_t sb = sbk[e] != 0xFFFFFFFFu ? sbk[e] : 0u;
-                rlo[e] = sub_hist[sb];
-                rhi[e] = sbk[e] != 0xFFFFFFFFu ? sub_hist[sb + 1] : rlo[e];
+                const bool ok = sbk[e] != 0xFFFFFFFFu;
+                const uint32_t sb = ok ? sbk[e] : 0u;
+                const uint32_t lo = sub_hist[sb], hi = sub_hist[sb + 1];
+                rlo[e] = lo;
+                rhi[e] = ok ? hi : lo;
             }
+            // the window compares only the key-bit words (the high word of
+            // each entry); a record meets its own entry once, so two or more
+            // equal words mean another record with the same stored bits
+            const uint32_t *KW = reinterpret_cast<const uint32_t *>(pool) + 1;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const uint32_t hm = (uint32_t)key[e];
-                uint32_t r = 0;
+                uint32_t hq[RW];
+#pragma unroll
+                for (uint32_t j = 0; j < RW; ++j)
+                    hq[j] = KW[2u * min(rlo[e] + j, (uint32_t)CAP - 1u)];
+                uint32_t r = 0, eq = 0;
 #pragma unroll
                 for (uint32_t j = 0; j < RW; ++j) {
-                    const uint64_t w = KS[min(rlo[e] + j, (uint32_t)CAP - 1u)];
-                    const uint32_t hq = (uint32_t)(w >> 32);
                     const bool in = rlo[e] + j < rhi[e];
-                    r += in && hq < hm;
-                    if (in && hq == hm && (uint32_t)w != sid[e])
-                        tie |= 1u << e;
+                    r += in && hq[j] < hm;
+                    eq += in && hq[j] == hm;
                 }
                 for (uint32_t q = rlo[e] + RW; q < rhi[e]; ++q) {
-                    const uint64_t w = KS[q];
-                    const uint32_t hq = (uint32_t)(w >> 32);
-                    r += hq < hm;
-                    if (hq == hm && (uint32_t)w != sid[e])
-                        tie |= 1u << e;
+                    const uint32_t h = KW[2u * q];
+                    r += h < hm;
+                    eq += h == hm;
                 }
+                if (eq > 1)
+                    tie |= 1u << e;
                 fp[e] = rlo[e] + r;
             }
             if (tie) {
