@@ -1199,9 +1199,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     // afterwards the fused mode's bound codes in sorted order (their ids go
     // to the sub-bucket table, dead by then)
     constexpr int POOL = FUSED ? 8 * CAP : 12 * CAP;
-    // (32 bytes past the end: the rank windows read up to RW - 1 = 3
-    // entries past the last one, unclamped, and ignore them)
-    __shared__ __align__(16) unsigned char pool[POOL + 32];
+    __shared__ __align__(16) unsigned char pool[POOL];
     static_assert(CAP < 65536, "16-bit sub-bucket sums and candidate positions");
     static_assert(2 * (NSUB + 2) >= 4 * (CAP / 2), "candidate list fits the sub-bucket table");
     static_assert(2 * CAP + 4 * (MAX_TILES + 1) + 4 * MAX_TILES <= POOL,
@@ -1220,6 +1218,8 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     constexpr bool fused = FUSED;
     const uint32_t rank0 = a.bucket_start[b0];
     const uint32_t tot = a.bucket_start[b1] - rank0;
+    // (read here, so that the load overlaps the table loads below)
+    const uint32_t step = step_of(a.step, a.step_dev);
     if (tid == 0) {
         s_misc[2] = 0;
         s_misc[3] = 0;  // listed candidate pairs (fused LDS path)
@@ -1239,11 +1239,25 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     }
 
     // 1. this group's run in each of those tiles; bucket and cell tables
-    for (int t = tid; t < ntl; t += THREADS) {
-        const uint32_t lo = tile_bucket_off(a, t_first + t, b0);
-        const uint32_t hi = tile_bucket_off(a, t_first + t, b1);
-        run_base[t] = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
-        run_pre[t] = hi - lo;
+    if (!a.tile_lb) {  // dense tables: both offsets load together
+        for (int t = tid; t < ntl; t += THREADS) {
+            const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
+            const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
+            run_base[t] = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
+            run_pre[t] = hi - lo;
+        }
+    } else {  // local tables (tile_bucket_off for b0 and b1, branch-free)
+        for (int t = tid; t < ntl; t += THREADS) {
+            const int tt = t_first + t;
+            const int lb = a.tile_lb[tt], tnb = a.tile_nb[tt];
+            const uint32_t loff = a.tile_loff[tt];
+            const int i0 = min(max(b0 - lb, 0), tnb), i1 = min(max(b1 - lb, 0), tnb);
+            const uint32_t v0 = a.tile_off[loff + (uint32_t)i0];
+            const uint32_t v1 = a.tile_off[loff + (uint32_t)i1];
+            const uint32_t lo = b0 <= lb ? 0u : v0, hi = b1 <= lb ? 0u : v1;
+            run_base[t] = (uint32_t)tt * (uint32_t)a.tile + lo;
+            run_pre[t] = hi - lo;
+        }
     }
     for (int i = tid; i <= nb; i += THREADS)
         t_off[i] = a.bucket_start[b0 + i] - rank0;
@@ -1347,7 +1361,6 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         // repeat the last record and are dropped below), so that the loads
         // of all EPT records are in flight together
         const uint32_t last = tot > 0 ? tot - 1 : 0;
-        const uint32_t step = step_of(a.step, a.step_dev);
         // fused mode: phi of this thread's pairs (k = 2j, 2j + 1, j = tid +
         // it THREADS), drawn while the records are in flight
         constexpr int PITER = (CAP / 2 + 2 * THREADS - 1) / (2 * THREADS);
@@ -1693,7 +1706,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                         ((uint32_t)a.rec_f[pos] & ((1u << RF_BKT_SHIFT) - 1u))
                   : a.rec_k[pos].s;
         const uint64_t k =
-            fused ? shuffle_key(a, s, step_of(a.step, a.step_dev)) : a.rec_k[pos].key;
+            fused ? shuffle_key(a, s, step) : a.rec_k[pos].key;
         a.sk[base2 + li] = k;
         a.ss[base2 + li] = s;
         a.sb[base2 + li] = local_bucket(a, b0, nb, k, s);
