@@ -1259,9 +1259,13 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             run_pre[t] = hi - lo;
         }
     }
-    for (int i = tid; i <= nb; i += THREADS)
+    // the bucket, cell and per-bucket tables start on other waves than the
+    // runs (a thread index rotated by whole waves), so that their load
+    // chains run side by side
+    auto rot = [&](int k) { return (tid + (k % (THREADS / 64)) * 64) % THREADS; };
+    for (int i = rot(4); i <= nb; i += THREADS)
         t_off[i] = a.bucket_start[b0 + i] - rank0;
-    for (int i = tid; i <= n_gc; i += THREADS) {
+    for (int i = rot(5); i <= n_gc; i += THREADS) {
         const int c = c_lo + i;
         if (i < n_gc) {
             g_cbb[i] = (uint32_t)a.cell_bucket_base[c];
@@ -1271,7 +1275,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         if (a.seg_off)
             g_seg[i] = a.seg_off[c];
     }
-    for (int i = tid; i < nb; i += THREADS) {
+    for (int i = rot(6); i < nb; i += THREADS) {
         const int b = b0 + i;
         const int c = a.bucket_cell[b];
         const int h = a.cell_h[c];
@@ -1285,10 +1289,10 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         const uint32_t n_c = a.bucket_start[last] - cs;
         t_cs[i] = cs;
         t_n[i] = n_c;
-        if (b == first)
-            a.cell_start[c] = cs;
         if (fused)
             t_pc[i] = pair_ctx(a, c, cs, n_c);
+        if (b == first)
+            a.cell_start[c] = cs;
     }
     __syncthreads();
     lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, ntl, red);
