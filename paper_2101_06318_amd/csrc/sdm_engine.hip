@@ -1440,22 +1440,47 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 cod[e] = 0;
             }
         }
+        if (fused && tot == 0) {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t li = (uint32_t)(e * THREADS + tid);
-            sbk[e] = 0xFFFFFFFFu;
-            blk[e] = 0;
-            gcl[e] = 0;
-            fp[e] = 0;
-            if (li < tot) {
-                uint32_t bl;
-                if (fused) {
-                    // the bucket from its low 5 bits (a group spans <= 32
-                    // buckets); key[] keeps the 24 key bits
-                    bl = ((uint32_t)key[e] - (uint32_t)b0) & 31u;
-                    key[e] = (key[e] >> (RF_KEY_SHIFT - RF_BKT_SHIFT)) & 0xFFFFFFu;
-                    gcl[e] = t_cl[bl];
-                } else {
+            for (int e = 0; e < EPT; ++e) {
+                sbk[e] = 0xFFFFFFFFu;
+                blk[e] = 0;
+                gcl[e] = 0;
+                fp[e] = 0;
+            }
+        } else if (fused) {
+            // the bucket from its low 5 bits (a group spans <= 32 buckets);
+            // key[] keeps the 24 key bits.  Branch-free over the EPT records
+            // (slots past tot hold the last record and count nothing), so
+            // that the table reads, then the counting atomics, are in
+            // flight together
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const bool ok = (uint32_t)(e * THREADS + tid) < tot;
+                const uint32_t bl = ((uint32_t)key[e] - (uint32_t)b0) & 31u;
+                key[e] = (key[e] >> (RF_KEY_SHIFT - RF_BKT_SHIFT)) & 0xFFFFFFu;
+                const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
+                gcl[e] = ok ? t_cl[bl] : (uint8_t)0;
+                blk[e] = ok ? (uint8_t)bl : (uint8_t)0;
+                sbk[e] = ok ? t_subbase[bl] + sub : 0xFFFFFFFFu;
+                // rank among equal sub-buckets: a 16-bit count in half of
+                // an LDS word (it never carries into the other half)
+                const uint32_t sh = (sbk[e] & 1u) * 16u;
+                // (a slot past tot adds 0 to a word of its own lane)
+                const uint32_t old =
+                    atomicAdd(&sub_w[ok ? sbk[e] >> 1 : (uint32_t)(tid & 63)], ok ? 1u << sh : 0u);
+                fp[e] = ok ? (old >> sh) & 0xFFFFu : 0u;
+            }
+        }
+        if (!fused) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t li = (uint32_t)(e * THREADS + tid);
+                sbk[e] = 0xFFFFFFFFu;
+                blk[e] = 0;
+                gcl[e] = 0;
+                fp[e] = 0;
+                if (li < tot) {
                     // the record's cell among the group's cells
                     int cl = 0;
                     if (a.seg_off)
@@ -1464,15 +1489,14 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                         cl = a.cell_id[sid[e]] - c_lo;
                     gcl[e] = (uint8_t)cl;
                     const uint32_t h = g_ch[cl];
-                    bl = g_cbb[cl] - (uint32_t)b0 + (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
+                    const uint32_t bl =
+                        g_cbb[cl] - (uint32_t)b0 + (h ? (uint32_t)(key[e] >> (53 - h)) : 0u);
+                    const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
+                    blk[e] = (uint8_t)bl;
+                    sbk[e] = t_subbase[bl] + sub;
+                    const uint32_t sh = (sbk[e] & 1u) * 16u;
+                    fp[e] = (atomicAdd(&sub_w[sbk[e] >> 1], 1u << sh) >> sh) & 0xFFFFu;
                 }
-                const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
-                blk[e] = (uint8_t)bl;
-                sbk[e] = t_subbase[bl] + sub;
-                // rank among equal sub-buckets: a 16-bit count in half of
-                // an LDS word (it never carries into the other half)
-                const uint32_t sh = (sbk[e] & 1u) * 16u;
-                fp[e] = (atomicAdd(&sub_w[sbk[e] >> 1], 1u << sh) >> sh) & 0xFFFFu;
             }
         }
         __syncthreads();
