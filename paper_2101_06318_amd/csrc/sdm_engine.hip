@@ -1238,13 +1238,21 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         ntl = s_hi > s_lo ? min(nt - 1, (int)((s_hi - 1) / tile)) - t_first + 1 : 0;
     }
 
-    // 1. this group's run in each of those tiles; bucket and cell tables
+    // 1. this group's run in each of those tiles; bucket and cell tables.
+    // With at most one run per thread the runs stay in registers until
+    // their scan, whose barrier also completes the tables
+    const bool runs_in_regs = ntl <= THREADS;
+    uint32_t r_base = 0, r_cnt = 0;  // run t = tid (runs_in_regs)
     if (!a.tile_lb) {  // dense tables: both offsets load together
         for (int t = tid; t < ntl; t += THREADS) {
             const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
             const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
-            run_base[t] = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
-            run_pre[t] = hi - lo;
+            r_base = (uint32_t)(t_first + t) * (uint32_t)a.tile + lo;
+            r_cnt = hi - lo;
+            if (!runs_in_regs) {
+                run_base[t] = r_base;
+                run_pre[t] = r_cnt;
+            }
         }
     } else {  // local tables (tile_bucket_off for b0 and b1, branch-free)
         for (int t = tid; t < ntl; t += THREADS) {
@@ -1255,8 +1263,12 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             const uint32_t v0 = a.tile_off[loff + (uint32_t)i0];
             const uint32_t v1 = a.tile_off[loff + (uint32_t)i1];
             const uint32_t lo = b0 <= lb ? 0u : v0, hi = b1 <= lb ? 0u : v1;
-            run_base[t] = (uint32_t)tt * (uint32_t)a.tile + lo;
-            run_pre[t] = hi - lo;
+            r_base = (uint32_t)tt * (uint32_t)a.tile + lo;
+            r_cnt = hi - lo;
+            if (!runs_in_regs) {
+                run_base[t] = r_base;
+                run_pre[t] = r_cnt;
+            }
         }
     }
     // the bucket, cell and per-bucket tables start on other waves than the
@@ -1294,10 +1306,24 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         if (b == first)
             a.cell_start[c] = cs;
     }
-    __syncthreads();
-    lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, ntl, red);
-    for (int t = tid; t < ntl; t += THREADS)
-        run_base[t] -= run_pre[t];  // modulo 2^32; run_base[t] + li is the slot
+    // (the sub-bucket counts start at zero; the next barrier orders this)
+    for (uint32_t i = tid; i < (uint32_t)(NSUB + 2) / 2; i += THREADS)
+        sub_w[i] = 0;
+    if (runs_in_regs) {
+        uint32_t all;
+        const uint32_t ex = block_exclusive_scan<THREADS>(r_cnt, red, &all);
+        if (tid < ntl) {
+            run_pre[tid] = ex;
+            run_base[tid] = r_base - ex;  // modulo 2^32; run_base[t] + li is the slot
+        }
+        if (tid == 0)
+            run_pre[ntl] = all;
+    } else {
+        __syncthreads();
+        lds_exclusive_scan<THREADS, (MAX_TILES + THREADS - 1) / THREADS>(run_pre, ntl, red);
+        for (int t = tid; t < ntl; t += THREADS)
+            run_base[t] -= run_pre[t];  // modulo 2^32; run_base[t] + li is the slot
+    }
     if (tid < 64) {  // nb <= MAXB <= 64: one wave scans the sub-bucket counts
         const uint32_t ns = tid < nb ? t_subbase[tid] : 0u;
         const uint32_t inc = wave_inclusive_scan(ns);
@@ -1330,8 +1356,6 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     const uint32_t cap_here =
         a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
     const bool lds_path = tot <= cap_here;
-    for (uint32_t i = tid; i < (uint32_t)(NSUB + 2) / 2; i += THREADS)
-        sub_w[i] = 0;
     __syncthreads();
 
     if (lds_path) {
