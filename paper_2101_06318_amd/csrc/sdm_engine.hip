@@ -1309,12 +1309,22 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     // (the sub-bucket counts start at zero; the next barrier orders this)
     for (uint32_t i = tid; i < (uint32_t)(NSUB + 2) / 2; i += THREADS)
         sub_w[i] = 0;
+    const uint32_t cap_here =
+        a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
+    const bool lds_path = tot <= cap_here;
+    // tile of each gathered slot (LDS path): with many short runs, each
+    // run's thread fills its own entries right after the scan
+    uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);
+    const bool own_fill = runs_in_regs && ntl > 8 && lds_path;
     if (runs_in_regs) {
         uint32_t all;
         const uint32_t ex = block_exclusive_scan<THREADS>(r_cnt, red, &all);
         if (tid < ntl) {
             run_pre[tid] = ex;
             run_base[tid] = r_base - ex;  // modulo 2^32; run_base[t] + li is the slot
+            if (own_fill)
+                for (uint32_t li = ex; li < ex + r_cnt; ++li)
+                    tmap[li] = (uint16_t)tid;
         }
         if (tid == 0)
             run_pre[ntl] = all;
@@ -1353,9 +1363,6 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         if (tid == 63)
             t_poff[nb] = pinc;
     }
-    const uint32_t cap_here =
-        a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
-    const bool lds_path = tot <= cap_here;
     __syncthreads();
 
     if (lds_path) {
@@ -1365,18 +1372,19 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         //    their sub-bucket
         uint64_t *K1 = reinterpret_cast<uint64_t *>(pool);
         uint32_t *S1 = reinterpret_cast<uint32_t *>(pool + 8 * CAP);
-        uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);  // tile of each gathered slot
         const uint32_t nsub = t_subbase[nb];
-        if (ntl <= 8) {  // a few long runs (batches): every thread on each
-            for (int t = 0; t < ntl; ++t)
-                for (uint32_t li = run_pre[t] + tid; li < run_pre[t + 1]; li += THREADS)
-                    tmap[li] = (uint16_t)t;
-        } else {         // many short runs: a thread per run
-            for (int t = tid; t < ntl; t += THREADS)
-                for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
-                    tmap[li] = (uint16_t)t;
+        if (!own_fill) {
+            if (ntl <= 8) {  // a few long runs (batches): every thread on each
+                for (int t = 0; t < ntl; ++t)
+                    for (uint32_t li = run_pre[t] + tid; li < run_pre[t + 1]; li += THREADS)
+                        tmap[li] = (uint16_t)t;
+            } else {         // many short runs: a thread per run
+                for (int t = tid; t < ntl; t += THREADS)
+                    for (uint32_t li = run_pre[t]; li < run_pre[t + 1]; ++li)
+                        tmap[li] = (uint16_t)t;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // fused mode: the record carries the 24 key bits below its bucket's
         // (bits 28 - h .. 52 - h) and the bucket's low 8 bits; they fix the
         // bucket and sub-bucket (u <= 24), and the rank falls back to the
