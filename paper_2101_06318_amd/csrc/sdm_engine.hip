@@ -96,6 +96,9 @@ struct TileArgs {
 
 struct GroupArgs {
     int mode;
+    int direct;                // one cell, dense tables, n_tiles <= group threads:
+                               // bucket starts summed from tile_off (no k_colsum)
+    const uint32_t *n_total;   // live SDs of the launch (the tiles' sum; direct)
     int32_t B;
     int32_t n_tiles;
     int32_t tile;
@@ -1183,6 +1186,8 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     __shared__ uint32_t t_pa[MAXB];        // first opener position of each bucket
     __shared__ uint32_t t_poff[MAXB + 1];  // pairs of the buckets before
     __shared__ uint8_t pair_bl[FUSED && !ONE_CELL ? CAP / 2 : 1];  // bucket of each pair
+    // direct starts: per-wave sums of the tiles' offsets of buckets b0 .. b1 - 1
+    __shared__ uint32_t colpart[ONE_CELL ? (THREADS / 64) * MAXB : 1];
     // cells of the group (c_lo + i): first bucket, key bits, run and, for
     // batches, first SD slot
     __shared__ uint32_t g_cbb[MAXB];
@@ -1216,8 +1221,15 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     const int nt = a.n_tiles;
     const int64_t Bp = a.B + 1;
     constexpr bool fused = FUSED;
-    const uint32_t rank0 = a.bucket_start[b0];
-    const uint32_t tot = a.bucket_start[b1] - rank0;
+    // a single cell with dense tables can take its bucket starts from the
+    // tiles' own offsets: bucket b starts at the sum over tiles of the
+    // tile's offset of b (known after the runs' scan below)
+    const bool direct = ONE_CELL && a.direct;
+    uint32_t rank0 = 0, tot = 0;
+    if (!direct) {
+        rank0 = a.bucket_start[b0];
+        tot = a.bucket_start[b1] - rank0;
+    }
     // (read here, so that the load overlaps the table loads below)
     const uint32_t step = step_of(a.step, a.step_dev);
     if (tid == 0) {
@@ -1243,7 +1255,17 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     // their scan, whose barrier also completes the tables
     const bool runs_in_regs = ntl <= THREADS;
     uint32_t r_base = 0, r_cnt = 0;  // run t = tid (runs_in_regs)
-    if (!a.tile_lb) {  // dense tables: both offsets load together
+    const bool dtv = tid < ntl;  // direct: this thread's tile and its offsets row
+    const uint16_t *drow = a.tile_off + (int64_t)(dtv ? tid : 0) * Bp + b0;
+    if (direct) {  // (ntl <= THREADS)
+        const uint32_t lo = drow[0], hi = drow[nb];
+        r_base = (uint32_t)tid * (uint32_t)a.tile + lo;
+        r_cnt = dtv ? hi - lo : 0u;
+        // rank0: the sum of the offsets of b0 (column 0)
+        const uint32_t ws = wave_scan_u32(dtv ? lo : 0u);  // lane 63: the sum
+        if ((tid & 63) == 63)
+            colpart[(tid >> 6) * MAXB] = ws;
+    } else if (!a.tile_lb) {  // dense tables: both offsets load together
         for (int t = tid; t < ntl; t += THREADS) {
             const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
             const uint32_t hi = a.tile_offT[(int64_t)b1 * nt + t_first + t];
@@ -1275,7 +1297,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     // runs (a thread index rotated by whole waves), so that their load
     // chains run side by side
     auto rot = [&](int k) { return (tid + (k % (THREADS / 64)) * 64) % THREADS; };
-    for (int i = rot(4); i <= nb; i += THREADS)
+    for (int i = rot(4); i <= nb && !direct; i += THREADS)
         t_off[i] = a.bucket_start[b0 + i] - rank0;
     for (int i = rot(5); i <= n_gc; i += THREADS) {
         const int c = c_lo + i;
@@ -1296,9 +1318,16 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         t_cl[i] = (uint8_t)(c - c_lo);
         t_mask[i] = (1u << u) - 1u;
         t_subbase[i] = 1u << u;
-        const int first = a.cell_bucket_base[c], last = a.cell_bucket_base[c + 1];
-        const uint32_t cs = a.bucket_start[first];
-        const uint32_t n_c = a.bucket_start[last] - cs;
+        int first = 0;
+        uint32_t cs = 0, n_c;
+        if (direct) {  // (one cell: buckets 0 .. B - 1, starting at rank 0)
+            n_c = *a.n_total;
+        } else {
+            first = a.cell_bucket_base[c];
+            const int last = a.cell_bucket_base[c + 1];
+            cs = a.bucket_start[first];
+            n_c = a.bucket_start[last] - cs;
+        }
         t_cs[i] = cs;
         t_n[i] = n_c;
         if (fused)
@@ -1311,14 +1340,44 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         sub_w[i] = 0;
     const uint32_t cap_here =
         a.group_cap >= 0 ? (uint32_t)min(a.group_cap, CAP) : (uint32_t)CAP;
-    const bool lds_path = tot <= cap_here;
     // tile of each gathered slot (LDS path): with many short runs, each
     // run's thread fills its own entries right after the scan
     uint16_t *tmap = reinterpret_cast<uint16_t *>(pool);
-    const bool own_fill = runs_in_regs && ntl > 8 && lds_path;
+    bool lds_path = tot <= cap_here, own_fill = false;
     if (runs_in_regs) {
         uint32_t all;
         const uint32_t ex = block_exclusive_scan<THREADS>(r_cnt, red, &all);
+        if (direct) {
+            uint32_t r0 = 0;
+#pragma unroll
+            for (int w = 0; w < THREADS / 64; ++w)
+                r0 += colpart[w * MAXB];
+            rank0 = r0;
+            tot = all;
+            lds_path = tot <= cap_here;
+            // the LDS path of one cell needs no bucket boundaries inside the
+            // group (its pairs follow the ranks across them); the global path
+            // sums the interior columns too
+            if (!lds_path) {
+                for (int i = 1; i < nb; ++i) {
+                    const uint32_t ws = wave_scan_u32(dtv ? (uint32_t)drow[i] : 0u);
+                    if ((tid & 63) == 63)
+                        colpart[(tid >> 6) * MAXB + i] = ws;
+                }
+                __syncthreads();
+            }
+            if (tid <= nb) {
+                uint32_t c = 0;
+                if (tid > 0 && tid < nb && !lds_path) {
+#pragma unroll
+                    for (int w = 0; w < THREADS / 64; ++w)
+                        c += colpart[w * MAXB + tid];
+                    c -= rank0;
+                }
+                t_off[tid] = tid == 0 ? 0u : tid == nb ? tot : c;
+            }
+        }
+        own_fill = ntl > 8 && lds_path;
         if (tid < ntl) {
             run_pre[tid] = ex;
             run_base[tid] = r_base - ex;  // modulo 2^32; run_base[t] + li is the slot
@@ -1345,7 +1404,18 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         // in-cell indices whose closer is in the same cell and in this
         // group; pair k of the group opens at t_pa[b] + 2 (k - t_poff[b])
         uint32_t cnt = 0;
-        if (tid < nb) {
+        if (direct) {
+            // one cell, its ranks rank0 .. rank0 + tot - 1 as one range (the
+            // openers of every bucket, counted together)
+            if (tid == 0) {
+                const uint32_t fa = rank0 & 1u;  // (the cell starts at rank 0)
+                if (tot > 0) {
+                    const uint32_t lim = min(tot - 1u, t_n[0] - 1u - rank0);
+                    cnt = fa < lim ? (lim - fa + 1u) >> 1 : 0u;
+                }
+                t_pa[0] = fa;
+            }
+        } else if (tid < nb) {
             const uint32_t lo = t_off[tid], hi = t_off[tid + 1];
             const uint32_t cs = t_cs[tid];
             const uint32_t fa = lo + ((rank0 + lo - cs) & 1u);
@@ -1665,7 +1735,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             uint32_t state = 0;
             for (int end = 0; end < 2; ++end) {
                 const uint32_t f = end ? tot - 1u : 0u;
-                const int bl = upper_index(t_off, nb, f);
+                const int bl = ONE_CELL ? 0 : upper_index(t_off, nb, f);
                 const uint32_t cs = t_cs[bl];
                 const uint32_t ic = rank0 + f - cs;
                 const bool seam = end ? ((ic & 1u) == 0u && ic + 1u < t_n[bl]) : (ic & 1u) != 0u;
@@ -2536,7 +2606,10 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.rec_k = p->rec_k;
     ta.rec_f = p->rec_f;
     ta.chunk = p->chunk;
-    ta.start_zero = (p->n_tiles > 64 && !p->tile_lb) ? p->bucket_start : nullptr;
+    // a fused single-cell launch with dense tables and at most one tile per
+    // group thread: the group kernel sums its bucket starts itself
+    const bool direct = !list && p->n_cell == 1 && !p->tile_lb && p->n_tiles <= GROUP_THREADS;
+    ta.start_zero = (p->n_tiles > 64 && !p->tile_lb && !direct) ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
     const size_t lds = (size_t)tile_hist_bytes(p->lhist) + (size_t)p->chunk * sizeof(RecK);
@@ -2560,7 +2633,7 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
         hipLaunchKernelGGL((k_colsum_batch<256>), dim3((p->B + 1 + 255) / 256), dim3(256), 0,
                            stream, sa);
         SDM_HIP(hipGetLastError());
-    } else {
+    } else if (!direct) {
         ScanArgs sa{};
         sa.tile_off = p->tile_off;
         sa.tile_offT = p->tile_offT;
@@ -2574,6 +2647,8 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
 
     GroupArgs ga{};
     ga.mode = p->mode;
+    ga.direct = direct ? 1 : 0;
+    ga.n_total = p->n_acc;
     ga.B = p->B;
     ga.n_tiles = p->n_tiles;
     ga.tile = p->tile;
