@@ -1884,6 +1884,9 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
     const int g = blockIdx.x * THREADS + threadIdx.x;
     Stats st{0, 0, 0, 0, 0};
     const bool fused = a.mode == MODE_FUSED;
+    // the live total, loaded at once (its use is the block's last step)
+    const bool keeper = blockIdx.x == 0 && threadIdx.x == 0;
+    const uint32_t n_live = keeper ? a.n_acc[0] : 0u;
     if (fused && g < a.G) {
         // the next group's records are read before knowing they are needed
         // (one dependent round trip instead of three)
@@ -1929,8 +1932,8 @@ __global__ __launch_bounds__(THREADS) void k_finish(FinishArgs a)
     }
     if (fused && a.counters)
         flush_stats<THREADS>(st, a.counters, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const uint32_t n = a.n_acc[0];
+    if (keeper) {
+        const uint32_t n = n_live;
         *a.n_live_out = (int64_t)n;
         a.cell_start[a.n_cell] = n;
         a.n_acc[0] = 0;
