@@ -96,8 +96,9 @@ struct TileArgs {
 
 struct GroupArgs {
     int mode;
-    int direct;                // one cell, dense tables, n_tiles <= group threads:
-                               // bucket starts summed from tile_off (no k_colsum)
+    int direct;                // one cell or groups of whole cells, dense tables,
+                               // n_tiles <= group threads: bucket starts summed
+                               // from tile_off (no k_colsum)
     const uint32_t *n_total;   // live SDs of the launch (the tiles' sum; direct)
     int32_t B;
     int32_t n_tiles;
@@ -1170,7 +1171,7 @@ __device__ __forceinline__ float float_below(double x)
 // --------------------------------------------------------------- k_group
 // The usual fused plans (seven records per thread, 39 KB of LDS) run three
 // workgroups per CU: at most 80 VGPRs, six waves per SIMD.
-template <int THREADS, int EPT, bool FUSED, bool ONE_CELL = false>
+template <int THREADS, int EPT, bool FUSED, bool ONE_CELL = false, bool WHOLE = false>
 __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(GroupArgs a)
 {
     constexpr int CAP = THREADS * EPT;
@@ -1187,7 +1188,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     __shared__ uint32_t t_poff[MAXB + 1];  // pairs of the buckets before
     __shared__ uint8_t pair_bl[FUSED && !ONE_CELL ? CAP / 2 : 1];  // bucket of each pair
     // direct starts: per-wave sums of the tiles' offsets of buckets b0 .. b1 - 1
-    __shared__ uint32_t colpart[ONE_CELL ? (THREADS / 64) * MAXB : 1];
+    __shared__ uint32_t colpart[FUSED && (ONE_CELL || WHOLE) ? (THREADS / 64) * MAXB : 1];
     // cells of the group (c_lo + i): first bucket, key bits, run and, for
     // batches, first SD slot
     __shared__ uint32_t g_cbb[MAXB];
@@ -1221,10 +1222,13 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     const int nt = a.n_tiles;
     const int64_t Bp = a.B + 1;
     constexpr bool fused = FUSED;
-    // a single cell with dense tables can take its bucket starts from the
-    // tiles' own offsets: bucket b starts at the sum over tiles of the
-    // tile's offset of b (known after the runs' scan below)
-    const bool direct = ONE_CELL && a.direct;
+    // with dense tables, a single cell, or groups of whole cells, can take
+    // their bucket starts from the tiles' own offsets: bucket b starts at
+    // the sum over tiles of the tile's offset of b (known after the runs'
+    // scan below)
+    // (WHOLE: the instance for groups of whole cells)
+    const bool direct = FUSED && (ONE_CELL || WHOLE) && a.direct;
+    const bool directm = direct && WHOLE && !ONE_CELL;
     uint32_t rank0 = 0, tot = 0;
     if (!direct) {
         rank0 = a.bucket_start[b0];
@@ -1265,6 +1269,20 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         const uint32_t ws = wave_scan_u32(dtv ? lo : 0u);  // lane 63: the sum
         if ((tid & 63) == 63)
             colpart[(tid >> 6) * MAXB] = ws;
+        if (directm) {  // every bucket's start: columns 1 .. nb - 1 too
+            uint32_t v[MAXB];
+#pragma unroll
+            for (int j = 1; j < MAXB; ++j)
+                v[j] = dtv ? (uint32_t)drow[min(j, nb)] : 0u;
+#pragma unroll
+            for (int j = 1; j < MAXB; ++j) {
+                if (j < nb) {
+                    const uint32_t wj = wave_scan_u32(v[j]);
+                    if ((tid & 63) == 63)
+                        colpart[(tid >> 6) * MAXB + j] = wj;
+                }
+            }
+        }
     } else if (!a.tile_lb) {  // dense tables: both offsets load together
         for (int t = tid; t < ntl; t += THREADS) {
             const uint32_t lo = a.tile_offT[(int64_t)b0 * nt + t_first + t];
@@ -1320,7 +1338,13 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         t_subbase[i] = 1u << u;
         int first = 0;
         uint32_t cs = 0, n_c;
-        if (direct) {  // (one cell: buckets 0 .. B - 1, starting at rank 0)
+        if (directm) {
+            // the cell's buckets (inside the group) for now; its start, its
+            // size and the pair constants that need them follow the scan
+            first = a.cell_bucket_base[c];
+            cs = (uint32_t)(first - b0);
+            n_c = (uint32_t)(a.cell_bucket_base[c + 1] - b0);
+        } else if (direct) {  // (one cell: buckets 0 .. B - 1, starting at rank 0)
             n_c = *a.n_total;
         } else {
             first = a.cell_bucket_base[c];
@@ -1330,9 +1354,10 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         }
         t_cs[i] = cs;
         t_n[i] = n_c;
+        // (directm: norm = dt / dV_c for now, F(2) = 1; times F(n_c) below)
         if (fused)
-            t_pc[i] = pair_ctx(a, c, cs, n_c);
-        if (b == first)
+            t_pc[i] = directm ? pair_ctx(a, c, 0u, 2u) : pair_ctx(a, c, cs, n_c);
+        if (b == first && !directm)
             a.cell_start[c] = cs;
     }
     // (the sub-bucket counts start at zero; the next barrier orders this)
@@ -1358,7 +1383,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             // the LDS path of one cell needs no bucket boundaries inside the
             // group (its pairs follow the ranks across them); the global path
             // sums the interior columns too
-            if (!lds_path) {
+            if (!lds_path && !directm) {
                 for (int i = 1; i < nb; ++i) {
                     const uint32_t ws = wave_scan_u32(dtv ? (uint32_t)drow[i] : 0u);
                     if ((tid & 63) == 63)
@@ -1368,7 +1393,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             }
             if (tid <= nb) {
                 uint32_t c = 0;
-                if (tid > 0 && tid < nb && !lds_path) {
+                if (tid > 0 && tid < nb && (!lds_path || directm)) {
 #pragma unroll
                     for (int w = 0; w < THREADS / 64; ++w)
                         c += colpart[w * MAXB + tid];
@@ -1394,6 +1419,37 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
             run_base[t] -= run_pre[t];  // modulo 2^32; run_base[t] + li is the slot
     }
     if (tid < 64) {  // nb <= MAXB <= 64: one wave scans the sub-bucket counts
+        // groups of whole cells (directm): each bucket's start (lane i: bucket
+        // b0 + i, from rank0), then its cell's start and size, the pair
+        // constants that need them and the cell's entry of cell_start
+        uint32_t dm_lo = 0, dm_hi = 0, dm_cs = 0, dm_n = 0;
+        if (directm) {
+            uint32_t col = 0;
+            if (tid > 0 && tid < nb) {
+#pragma unroll
+                for (int w = 0; w < THREADS / 64; ++w)
+                    col += colpart[w * MAXB + tid];
+                col -= rank0;
+            } else if (tid == nb) {
+                col = tot;
+            }
+            const int fi = tid < nb ? (int)t_cs[tid] : 0;  // the cell's first bucket
+            const int la = tid < nb ? (int)t_n[tid] : 0;   // and one past its last
+            const uint32_t cs_rel = (uint32_t)__shfl((int)col, fi);
+            const uint32_t ce_rel = (uint32_t)__shfl((int)col, la);
+            dm_hi = (uint32_t)__shfl((int)col, min(tid + 1, 63));
+            dm_lo = col;
+            dm_cs = rank0 + cs_rel;
+            dm_n = ce_rel - cs_rel;
+            if (tid < nb) {
+                t_cs[tid] = dm_cs;
+                t_n[tid] = dm_n;
+                t_pc[tid].norm = t_pc[tid].norm * (double)pair_scale((uint64_t)dm_n);
+                t_pc[tid].slot_base = a.slot_cell_local ? dm_cs : 0u;
+                if (fi == tid)
+                    a.cell_start[c_lo + (int)t_cl[tid]] = dm_cs;
+            }
+        }
         const uint32_t ns = tid < nb ? t_subbase[tid] : 0u;
         const uint32_t inc = wave_inclusive_scan(ns);
         if (tid < nb)
@@ -1404,7 +1460,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         // in-cell indices whose closer is in the same cell and in this
         // group; pair k of the group opens at t_pa[b] + 2 (k - t_poff[b])
         uint32_t cnt = 0;
-        if (direct) {
+        if (direct && ONE_CELL) {
             // one cell, its ranks rank0 .. rank0 + tot - 1 as one range (the
             // openers of every bucket, counted together)
             if (tid == 0) {
@@ -1416,13 +1472,15 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 t_pa[0] = fa;
             }
         } else if (tid < nb) {
-            const uint32_t lo = t_off[tid], hi = t_off[tid + 1];
-            const uint32_t cs = t_cs[tid];
+            const uint32_t lo = directm ? dm_lo : t_off[tid];
+            const uint32_t hi = directm ? dm_hi : t_off[tid + 1];
+            const uint32_t cs = directm ? dm_cs : t_cs[tid];
+            const uint32_t n_c = directm ? dm_n : t_n[tid];
             const uint32_t fa = lo + ((rank0 + lo - cs) & 1u);
             if (lo < hi) {
                 // openers f < lim: f < hi, f + 1 < tot, rank0 + f + 1 < cs + n_c
                 uint32_t lim = min(hi, tot - 1u);
-                lim = min(lim, cs + t_n[tid] - 1u - rank0);
+                lim = min(lim, cs + n_c - 1u - rank0);
                 cnt = fa < lim ? (lim - fa + 1u) >> 1 : 0u;
             }
             t_pa[tid] = fa;
@@ -2330,6 +2388,14 @@ static Plan *build_plan(sdm_ctx *ctx, int mode, int64_t n_items,
             }
             group_first.push_back(B);
         }
+        // groups that begin at a cell's first bucket and end after a cell's
+        // last one (then a group finds its cells' starts in its own columns)
+        p->whole_cells = true;
+        for (size_t gi = 0; gi + 1 < group_first.size(); ++gi) {
+            const int32_t f = group_first[gi], l = group_first[gi + 1];
+            if (cell_bb[bucket_cell[f]] != f || cell_bb[bucket_cell[l - 1] + 1] != l)
+                p->whole_cells = false;
+        }
         choose_tiles(p, n_items, tile_ept_max, batched ? 0 : B);
         p->B = B;
         p->lhist = B;
@@ -2609,9 +2675,11 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ta.rec_k = p->rec_k;
     ta.rec_f = p->rec_f;
     ta.chunk = p->chunk;
-    // a fused single-cell launch with dense tables and at most one tile per
-    // group thread: the group kernel sums its bucket starts itself
-    const bool direct = !list && p->n_cell == 1 && !p->tile_lb && p->n_tiles <= GROUP_THREADS;
+    // a fused launch of one cell, or of groups of whole cells, with dense
+    // tables and at most one tile per group thread: the group kernel sums
+    // its bucket starts itself
+    const bool direct = !list && (p->n_cell == 1 || p->whole_cells) && !p->tile_lb &&
+                        p->n_tiles <= GROUP_THREADS;
     ta.start_zero = (p->n_tiles > 64 && !p->tile_lb && !direct) ? p->bucket_start : nullptr;
     ta.n_acc = p->n_acc;
     ta.err = ctx->err_dev;
@@ -2703,8 +2771,12 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
     ga.group_stats = p->group_stats;
     mark(1);
     const bool one = p->n_cell == 1;
+    const bool whole = direct && !one;  // the instance for groups of whole cells
     if (p->gept == GROUP_EPT_L && !list && one)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true, true>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (p->gept == GROUP_EPT_L && !list && whole)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true, false, true>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     else if (p->gept == GROUP_EPT_L && !list)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_L, true>), dim3(p->G),
@@ -2714,6 +2786,9 @@ void engine_run(sdm_ctx *ctx, Plan *p, const StepInputs &in, hipStream_t stream)
                            dim3(GROUP_THREADS), 0, stream, ga);
     else if (!list && one)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true, true>), dim3(p->G),
+                           dim3(GROUP_THREADS), 0, stream, ga);
+    else if (!list && whole)
+        hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true, false, true>), dim3(p->G),
                            dim3(GROUP_THREADS), 0, stream, ga);
     else if (!list)
         hipLaunchKernelGGL((k_group<GROUP_THREADS, GROUP_EPT_S, true>), dim3(p->G),

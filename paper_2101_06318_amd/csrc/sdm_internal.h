@@ -136,6 +136,7 @@ struct Plan {
     uint64_t *rec_f = nullptr;            // fused mode records (8 B)
     uint32_t chunk = 0;                   // records per LDS staging pass of the tile kernel
     int gept = 0;                         // records per group-kernel thread (4 or 8)
+    bool whole_cells = false;             // every group holds whole cells
     uint32_t *n_acc = nullptr;            // [0] live total, [3] finish-kernel done counter
     uint32_t *bucket_start = nullptr;     // [B+1] global start rank per bucket
     uint32_t *cell_start_ws = nullptr;    // [C+1]
