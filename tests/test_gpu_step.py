@@ -141,6 +141,18 @@ def test_step_grid_static_cells(sdm):
     ctx.close()
 
 
+@pytest.mark.parametrize("mean", [1500.0, 3000.0])
+def test_step_grid_of_multi_bucket_cells(sdm, mean):
+    """Cells of two or four buckets each, so that a group of about 3000 SDs
+    holds whole cells (two cells of two buckets, or one of four) and sums
+    its cells' bucket starts from the tiles' own offsets: two steps against
+    the oracle, element by element (cell starts included)."""
+    w = workloads.grid(seed=11, nx=8, ny=8, mean_per_cell=mean, n_max=4 * int(mean))
+    ctx = sdm.Context(w["n_sd"], w["n_cell"], 2)
+    _run_pair(sdm, ctx, w, 2, seed=11)
+    ctx.close()
+
+
 @pytest.mark.parametrize("caps", [(32, -1), (0, 64), (16, 40)])
 def test_step_overflow_and_global_sort_paths(sdm, caps):
     """Tiny bucket regions / group capacities force the overflow list and the
