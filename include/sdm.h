@@ -319,7 +319,9 @@ typedef struct {
                                      /* and after it, for timing            */
 } sdm_step_params;
 
-/* One whole timestep (workflow figure, Steps 0-3) in four kernels, with the
+/* One whole timestep (workflow figure, Steps 0-3) in four kernels (three
+ * when every group of the plan holds one cell or whole cells and the plan
+ * has at most 512 tiles: no column-sum kernel), with the
  * result of running the routines above in the paper's order with inline
  * random numbers: the live set is {s : xi[s] > 0} (Step 0), idx receives
  * the live SDs sorted by (cell, shuffle key, s), the pairs and slots are
