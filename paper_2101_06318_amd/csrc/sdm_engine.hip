@@ -1241,8 +1241,9 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
         s_misc[3] = 0;  // listed candidate pairs (fused LDS path)
     }
 
-    const int c_lo = a.bucket_cell[b0];
-    const int n_gc = a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
+    // (one cell: cell 0, no lookups)
+    const int c_lo = ONE_CELL ? 0 : a.bucket_cell[b0];
+    const int n_gc = ONE_CELL ? 1 : a.bucket_cell[b1 - 1] - c_lo + 1;  // <= nb <= MAXB
     // the tiles that can hold the group's records: all of them, except in a
     // batch, whose runs occupy contiguous slot ranges (tiles t_first ..
     // t_first + ntl - 1)
@@ -1329,7 +1330,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     }
     for (int i = rot(6); i < nb; i += THREADS) {
         const int b = b0 + i;
-        const int c = a.bucket_cell[b];
+        const int c = ONE_CELL ? 0 : a.bucket_cell[b];
         const int h = a.cell_h[c];
         const int u = a.sub_bits[b];
         t_shift[i] = (uint32_t)(fused ? 24 - u : 53 - h - u);
