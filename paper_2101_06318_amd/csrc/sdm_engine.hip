@@ -1621,7 +1621,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 const uint32_t bl = ((uint32_t)key[e] - (uint32_t)b0) & 31u;
                 key[e] = (key[e] >> (RF_KEY_SHIFT - RF_BKT_SHIFT)) & 0xFFFFFFu;
                 const uint32_t sub = (uint32_t)(key[e] >> t_shift[bl]) & t_mask[bl];
-                gcl[e] = ok ? t_cl[bl] : (uint8_t)0;
+                gcl[e] = ok && !ONE_CELL ? t_cl[bl] : (uint8_t)0;  // (one cell: cell 0)
                 blk[e] = ok ? (uint8_t)bl : (uint8_t)0;
                 sbk[e] = ok ? t_subbase[bl] + sub : 0xFFFFFFFFu;
                 // rank among equal sub-buckets: a 16-bit count in half of
