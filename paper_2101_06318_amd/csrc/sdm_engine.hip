@@ -1168,6 +1168,14 @@ __device__ __forceinline__ float float_below(double x)
     return (double)f > x ? __uint_as_float(__float_as_uint(f) - 1u) : f;
 }
 
+// x >= 0 rounded up to single precision (NaN stays NaN, beyond the float
+// range +inf), for testing a bound against phi held as float_below(phi)
+__device__ __forceinline__ float float_above(double x)
+{
+    const float f = (float)x;
+    return (double)f < x ? __uint_as_float(__float_as_uint(f) + 1u) : f;
+}
+
 // --------------------------------------------------------------- k_group
 // The usual fused plans (seven records per thread, 39 KB of LDS) run three
 // workgroups per CU: at most 80 VGPRs, six waves per SIMD.
@@ -1848,7 +1856,11 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 }
                 const PairCtx &pc = t_pc[bl];
                 const double pub = pair_bound(pc, RC[sw(f)], RC[sw(f + 1)]);
-                if (pub < (double)phi_pre[it][u]) {  // gamma = -0.0: no collision
+                // (several cells: the test in single precision, pub rounded
+                // up, so that no doubles of phi wait in registers)
+                const bool below = ONE_CELL ? pub < (double)phi_pre[it][u]
+                                            : float_above(pub) < phi_pre[it][u];
+                if (below) {  // gamma = -0.0: no collision
                     st.pairs += 1;
                     if (a.gamma_out)
                         a.gamma_out[pc.gbase + ((rank0 + f - pc.slot_base) >> 1)] = -0.0;
