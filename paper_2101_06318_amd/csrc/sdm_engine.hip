@@ -1195,6 +1195,9 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
     __shared__ uint32_t t_pa[MAXB];        // first opener position of each bucket
     __shared__ uint32_t t_poff[MAXB + 1];  // pairs of the buckets before
     __shared__ uint8_t pair_bl[FUSED && !ONE_CELL ? CAP / 2 : 1];  // bucket of each pair
+    // groups of whole cells: each pair's phi (rounded down) waits in LDS
+    // rather than in registers through the sort
+    __shared__ float phi_lds[FUSED && WHOLE ? CAP / 2 : 1];
     // direct starts: per-wave sums of the tiles' offsets of buckets b0 .. b1 - 1
     __shared__ uint32_t colpart[FUSED && (ONE_CELL || WHOLE) ? (THREADS / 64) * MAXB : 1];
     // cells of the group (c_lo + i): first bucket, key bits, run and, for
@@ -1588,6 +1591,12 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                             phi_pre[it][u] = float_below(word_to_uniform(
                                 philox_word(a.seed, runv[u], step, SDM_STREAM_GAMMA, qv[u])));
                 }
+                if (WHOLE) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (valid[u])
+                            phi_lds[2 * j + (uint32_t)u] = phi_pre[it][u];
+                }
             }
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -1859,7 +1868,7 @@ __global__ __launch_bounds__(THREADS, (FUSED && EPT <= 7) ? 6 : 4) void k_group(
                 // (several cells: the test in single precision, pub rounded
                 // up, so that no doubles of phi wait in registers)
                 const bool below = ONE_CELL ? pub < (double)phi_pre[it][u]
-                                            : float_above(pub) < phi_pre[it][u];
+                                            : float_above(pub) < (WHOLE ? phi_lds[k] : phi_pre[it][u]);
                 if (below) {  // gamma = -0.0: no collision
                     st.pairs += 1;
                     if (a.gamma_out)
